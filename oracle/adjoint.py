@@ -1,0 +1,47 @@
+"""Implicit adjoint of the LM optimum with respect to the observed pixels
+(oracle).
+
+At the optimum theta*, J^T r = 0 with r = u(theta) - px.  Differentiating
+with the Gauss-Newton Hessian and the solver's damping gives
+d theta*/d px = (J^T J + lambda D)^-1 J^T, hence for a loss L(theta*)
+with tangent gradient g_theta:
+    v = (J^T J + lambda D)^-1 g_theta,   dL/dpx_o = J_o v   (2 values / obs),
+because dr/dpx = -I.
+
+Pins (tests/test_oracle_adjoint.py): dense solve vs Schur solve, the
+gauge-projection identity (removing the D-weighted gauge part of g leaves
+J A^-1 g unchanged), central finite differences of the one-step linearised
+map, symmetric JVP/VJP dot test.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import camera, linear
+
+
+def implicit_grad_obs(state: camera.State, obs_cam, obs_pt, obs_px, g_theta: np.ndarray,
+                      lam: float, method: str = "schur") -> np.ndarray:
+    """dL/dpx [n_obs, 2] for the tangent gradient g_theta at state."""
+    r, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
+    J = linear.jacobian_csr(Jc, Jp, obs_cam, obs_pt, state.n_cams, state.n_points)
+    D = linear.damping_diagonal(J)
+    if method == "dense":
+        v = linear.solve_dense(J, D, lam, g_theta)
+    else:
+        v = linear.solve_schur(J, D, lam, g_theta, state.n_cams, state.n_points)
+    return (J @ v).reshape(-1, 2)
+
+
+def point_norm_loss_grad(state: camera.State) -> np.ndarray:
+    """Tangent gradient of L = sum |X_j|^2: zero on cameras, 2 X on points."""
+    g = np.zeros(state.n_params)
+    g[9 * state.n_cams:] = 2.0 * state.X.ravel()
+    return g
+
+
+def gauge_project(g: np.ndarray, N: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """g - D N (N^T D N)^-1 N^T g  (N: gauge vectors as rows, [7, N])."""
+    DN = D[None, :] * N
+    coef = np.linalg.solve(DN @ N.T, N @ g)
+    return g - DN.T @ coef

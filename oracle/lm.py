@@ -1,0 +1,130 @@
+"""Levenberg-Marquardt on the Snavely problem (oracle).
+
+Section V: LM with the quality-based (gain-ratio) damping update of Madsen
+et al., linearisation and retraction in the tangent space, normal equations
+(J^T J + lambda D) delta = -g solved without reduction on the GPU.  The
+oracle solves the same damped system exactly (dense or Schur Cholesky) or
+with the same PCG steps as the GPU (inner="pcg").
+
+One iteration = one inner solve plus one trial, accepted or not:
+  pred = 1/2 (b^T delta + delta^T r_inner + lambda delta^T D delta), b = -g
+  rho  = (F - F(theta (+) delta)) / pred
+  rho > 0 and pred > 0: accept, relinearise, lambda *= max(1/3, 1-(2 rho-1)^3),
+                        nu = 2
+  otherwise:            lambda *= nu, nu *= 2
+  lambda clamped to [lambda_min, lambda_max].
+Stops early when ||g||_inf <= grad_tol * max(1, ||g_0||_inf) or F <= min_cost.
+
+Defaults: lambda_0 = 1e-2, the inverse of the initial trust-region radius
+100 used in Section VI.
+
+Pins (tests/test_oracle_lm.py): zero-noise problems converge to F ~ 0,
+accepted costs decrease monotonically, the noisy optimum matches the
+chi-square expectation, an independent solver (scipy least_squares on an
+additive angle-axis parametrisation with its own residual) reaches the same
+final cost.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import camera, linear, pcg as pcg_mod
+
+
+@dataclasses.dataclass
+class LMOptions:
+    lambda0: float = 1e-2
+    max_iters: int = 20
+    inner: str = "schur"            # "dense" | "schur" | "pcg"
+    pcg_tol: float = 1e-6
+    pcg_max_iters: int = 500
+    lambda_min: float = 1e-12
+    lambda_max: float = 1e16
+    grad_tol: float = 1e-12
+    min_cost: float = 1e-30
+    nu_max: float = 2.0 ** 60
+
+
+@dataclasses.dataclass
+class LMIteration:
+    cost: float          # F after the iteration (current state)
+    trial_cost: float
+    lam: float           # lambda used in this iteration's solve
+    rho: float
+    pred: float
+    accepted: bool
+    inner_iters: int
+
+
+@dataclasses.dataclass
+class LMResult:
+    state: camera.State
+    initial_cost: float
+    final_cost: float
+    history: list
+    final_lambda: float
+    stop_reason: str
+
+
+def _linearize(state, obs_cam, obs_pt, obs_px):
+    r, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
+    J = linear.jacobian_csr(Jc, Jp, obs_cam, obs_pt, state.n_cams, state.n_points)
+    F = 0.5 * float(np.sum(r * r))
+    g = linear.gradient(J, r)
+    D = linear.damping_diagonal(J)
+    return F, J, g, D
+
+
+def solve_step(J, D, lam, b, n_cams, n_points, opts: LMOptions):
+    """Returns (delta, inner residual b - A delta, inner iterations)."""
+    if opts.inner == "dense":
+        x = linear.solve_dense(J, D, lam, b)
+        return x, np.zeros_like(b), 0
+    if opts.inner == "schur":
+        x = linear.solve_schur(J, D, lam, b, n_cams, n_points)
+        return x, np.zeros_like(b), 0
+    if opts.inner == "pcg":
+        Mc, Mp = linear.block_jacobi_inverse(J, D, lam, n_cams, n_points)
+        x, r, k, _ = pcg_mod.pcg(J, D, lam, b, Mc, Mp, opts.pcg_tol, opts.pcg_max_iters)
+        return x, r, k
+    raise ValueError(opts.inner)
+
+
+def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None = None) -> LMResult:
+    opts = opts or LMOptions()
+    state = state.copy()
+    F, J, g, D = _linearize(state, obs_cam, obs_pt, obs_px)
+    F0 = F
+    g0 = float(np.max(np.abs(g))) if g.size else 0.0
+    lam, nu = opts.lambda0, 2.0
+    history = []
+    reason = "max_iters"
+    for _ in range(opts.max_iters):
+        if float(np.max(np.abs(g))) <= opts.grad_tol * max(1.0, g0):
+            reason = "gradient"
+            break
+        if F <= opts.min_cost:
+            reason = "cost"
+            break
+        b = -g
+        delta, r_in, k = solve_step(J, D, lam, b, state.n_cams, state.n_points, opts)
+        pred = 0.5 * float(b @ delta + delta @ r_in + lam * delta @ (D * delta))
+        trial = state.retract(delta)
+        Ft = camera.cost(trial, obs_cam, obs_pt, obs_px)
+        rho = (F - Ft) / pred if (pred > 0.0 and np.isfinite(Ft)) else -np.inf
+        lam_used = lam
+        if rho > 0.0:
+            state = trial
+            F, J, g, D = _linearize(state, obs_cam, obs_pt, obs_px)
+            lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+            accepted = True
+        else:
+            lam *= nu
+            nu = min(2.0 * nu, opts.nu_max)
+            accepted = False
+        lam = min(max(lam, opts.lambda_min), opts.lambda_max)
+        history.append(LMIteration(F, Ft, lam_used, rho, pred, accepted, k))
+    return LMResult(state, F0, F, history, lam, reason)

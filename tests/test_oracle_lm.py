@@ -1,0 +1,93 @@
+"""Pins for the oracle LM (Section V: Levenberg-Marquardt with the gain-ratio
+damping update, tangent-space retraction)."""
+import numpy as np
+import pytest
+import scipy.optimize
+import scipy.sparse as sp
+from scipy.spatial.transform import Rotation
+
+from oracle import camera, lm
+from synth import scene_config
+
+from helpers import small_scene, observed_pixels
+
+
+def _solve(sc, noise_scale=1.0, **opts):
+    px = observed_pixels(sc, noise_scale)
+    st = camera.State.from_bal(sc.cams_init, sc.points_init)
+    return lm.solve(st, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(**opts)), px
+
+
+def test_zero_noise_converges_to_zero_cost():
+    sc = scene_config("tiny")
+    res, _ = _solve(sc, noise_scale=0.0, max_iters=20)
+    assert res.initial_cost > 1e3
+    assert res.final_cost <= 1e-20 * res.initial_cost
+
+
+@pytest.mark.parametrize("inner", ["schur", "pcg"])
+def test_accepted_costs_decrease_monotonically(inner):
+    sc = small_scene(n_cams=6, n_points=200, seed=11, k=4)
+    res, _ = _solve(sc, max_iters=15, inner=inner)
+    costs = [res.initial_cost] + [h.cost for h in res.history]
+    assert all(b <= a for a, b in zip(costs, costs[1:]))
+    prev = res.initial_cost
+    for h in res.history:
+        if h.accepted:
+            assert h.rho > 0 and h.cost == h.trial_cost < prev
+        else:
+            assert h.cost == prev
+        prev = h.cost
+    assert res.final_cost < 0.2 * res.initial_cost
+
+
+def test_dense_and_schur_steps_give_the_same_trajectory():
+    sc = small_scene(n_cams=3, n_points=25, seed=4, k=3)
+    a, _ = _solve(sc, max_iters=8, inner="dense")
+    b, _ = _solve(sc, max_iters=8, inner="schur")
+    for ha, hb in zip(a.history, b.history):
+        assert ha.accepted == hb.accepted
+        assert abs(ha.cost - hb.cost) <= 1e-9 * ha.cost
+
+
+def test_noisy_optimum_matches_chi_square_expectation():
+    # sigma = 1 px: E[2 F*] = 2 n_obs - (N - 7), std sqrt(2 (2 n_obs - N + 7))
+    sc = scene_config("tiny")
+    res, _ = _solve(sc, max_iters=20)
+    dof = 2 * sc.n_obs - (9 * sc.n_cams + 3 * sc.n_points - 7)
+    assert abs(2 * res.final_cost - dof) < 4 * np.sqrt(2 * dof)
+
+
+def _independent_residual(x, nc, npnt, obs_cam, obs_pt, px):
+    """BAL model written with scipy's rotation, additive angle-axis."""
+    cams = x[: 9 * nc].reshape(nc, 9)
+    X = x[9 * nc:].reshape(npnt, 3)
+    rot = Rotation.from_rotvec(cams[:, 0:3])
+    P = np.empty((obs_cam.size, 3))
+    for c in range(nc):
+        m = obs_cam == c
+        P[m] = rot[c].apply(X[obs_pt[m]]) + cams[c, 3:6]
+    p = -P[:, :2] / P[:, 2:3]
+    n2 = np.sum(p * p, axis=1, keepdims=True)
+    k1, k2, f = cams[obs_cam, 7:8], cams[obs_cam, 8:9], cams[obs_cam, 6:7]
+    return (f * (1 + k1 * n2 + k2 * n2 * n2) * p - px).ravel()
+
+
+@pytest.mark.slow
+def test_independent_least_squares_reaches_the_same_cost():
+    sc = scene_config("tiny")
+    res, px = _solve(sc, max_iters=30)
+    nc, npnt = sc.n_cams, sc.n_points
+    x0 = np.concatenate([sc.cams_init.ravel(), sc.points_init.ravel()])
+    rows = np.repeat(np.arange(2 * sc.n_obs), 12)
+    cols = np.concatenate([
+        (9 * sc.obs_cam[:, None] + np.arange(9)[None, :]),
+        (9 * nc + 3 * sc.obs_pt[:, None] + np.arange(3)[None, :])], axis=1)
+    cols = np.repeat(cols, 2, axis=0).ravel()
+    S = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(2 * sc.n_obs, x0.size))
+    out = scipy.optimize.least_squares(
+        _independent_residual, x0, jac="3-point", jac_sparsity=S, method="trf",
+        x_scale="jac", ftol=1e-15, xtol=1e-15, gtol=1e-15, max_nfev=200,
+        tr_options={"atol": 1e-14, "btol": 1e-14},
+        args=(nc, npnt, sc.obs_cam, sc.obs_pt, px))
+    assert abs(out.cost - res.final_cost) <= 1e-9 * res.final_cost, (out.cost, res.final_cost)
