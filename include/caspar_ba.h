@@ -1,0 +1,206 @@
+/*
+ * caspar_ba.h -- C ABI of the MI355X (gfx950) bundle-adjustment hot path.
+ *
+ * The library solves the bundle-adjustment problem of the paper's Section VI-A
+ * (Snavely reprojection factor: camera = pose + (f, k1, k2), point = R^3,
+ * residual = predicted pixel - observed pixel) with the solver of Section V:
+ * Levenberg-Marquardt with the gain-ratio damping update, tangent-space
+ * linearisation and retraction, and the damped normal equations solved
+ * directly (no Schur reduction) by block-Jacobi preconditioned conjugate
+ * gradients on the normal equations (PCGNR), one preconditioner block per
+ * camera and per point.
+ *
+ * Conventions shared by every call
+ *  - Pointers marked (dev) are device pointers on the GPU that was current
+ *    when the handle was created; (host) pointers are ordinary host memory.
+ *    The caller owns every pointer it passes.  create() copies its inputs.
+ *  - Cameras cross the boundary in BAL layout, 9 doubles per camera:
+ *    angle-axis rotation (3), translation (3), f, k1, k2.  Points are 3
+ *    doubles.  Observations are (camera index, point index, pixel x, y).
+ *    Every array at the boundary is float64 and in the caller's order.
+ *  - Tangent vectors (parity hooks, gradients) have length
+ *    N = 9 n_cams + 3 n_points, laid out [cameras | points] in caller
+ *    index order.  A camera's tangent is [dw(3), dt(3), df, dk1, dk2] with the
+ *    rotation perturbed on the right, R <- R Exp(dw); everything else is
+ *    additive.
+ *  - Every call enqueues its GPU work on the HIP stream given at create()
+ *    (NULL = the default stream) and returns when that work is complete.
+ *  - Every call returns CASPAR_OK (0) or a negative status; the message of
+ *    the last failure on the calling thread is caspar_last_error().  A failed
+ *    call leaves the handle usable unless the status is CASPAR_EHIP.
+ *  - Calls on one handle must not overlap (no internal locking).
+ */
+#ifndef CASPAR_BA_H
+#define CASPAR_BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define CASPAR_API __attribute__((visibility("default")))
+#else
+#define CASPAR_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct caspar_ba caspar_ba; /* opaque handle */
+
+/* Arithmetic of the hot path.
+ * CASPAR_FP64: everything in float64.
+ * CASPAR_FP32_MIXED: residuals, Jacobian blocks, the J / J^T products and the
+ *   PCG vectors in float32; float64 for the cost sums, the gain ratio, the PCG
+ *   dot products and alpha/beta, the block-Jacobi block sums and their
+ *   inversion, and the parameters themselves. */
+enum { CASPAR_FP64 = 0, CASPAR_FP32_MIXED = 1 };
+
+enum {
+  CASPAR_OK = 0,
+  CASPAR_EINVAL = -1,   /* bad argument, index out of range, non-finite input */
+  CASPAR_EHIP = -2,     /* a HIP runtime call failed */
+  CASPAR_ENOMEM = -3,   /* workspace smaller than caspar_ba_workspace_bytes() */
+  CASPAR_ENUMERIC = -4  /* non-finite cost or PCG breakdown at the first step */
+};
+
+/* Solver options; caspar_default_solve_opts() fills the defaults. */
+typedef struct caspar_solve_opts {
+  double lambda0;        /* initial damping; default 1e-2 = 1 / (trust radius 100, Sec. VI) */
+  double pcg_tol;        /* PCG stops when ||b - A x||_2 <= pcg_tol ||b||_2; default 1e-3 (Sec. VI) */
+  int32_t max_lm_iters;  /* LM iterations (an accepted or rejected trial each); default 20 */
+  int32_t max_pcg_iters; /* PCG iteration cap per LM iteration; default 500 */
+  double lambda_min;     /* damping clamp; default 1e-12 */
+  double lambda_max;     /* default 1e16 */
+  double grad_tol;       /* stop when ||g||_inf <= grad_tol * max(1, ||g_0||_inf); default 1e-12 */
+  double min_cost;       /* stop when the cost F <= min_cost; default 1e-30 */
+  int32_t pcg_check_every; /* host polls PCG convergence every this many iterations; default 4 */
+  int32_t flags;         /* reserved, 0 */
+} caspar_solve_opts;
+
+/* Per-solve statistics (host). */
+typedef struct caspar_solve_stats {
+  int32_t lm_iters;        /* iterations run (accepted + rejected) */
+  int32_t accepted;        /* accepted trials */
+  int32_t pcg_iters_total; /* PCG iterations (matrix products) over all LM iterations */
+  int32_t stop_reason;     /* 0 max iterations, 1 gradient, 2 cost */
+  double initial_cost;     /* F = 1/2 sum |r|^2 at the start */
+  double final_cost;       /* F at the returned parameters */
+  double final_lambda;
+  double seconds;          /* wall time of the solve (host clock, includes syncs) */
+} caspar_solve_stats;
+
+/* Per-LM-iteration record written by caspar_ba_solve when a history buffer
+ * is given (host, max_lm_iters entries). */
+typedef struct caspar_iter_record {
+  double cost;        /* F after the iteration */
+  double trial_cost;  /* F at theta (+) delta */
+  double lambda;      /* damping used for this iteration's solve */
+  double rho;         /* gain ratio (-inf when pred <= 0 or the trial is not finite) */
+  double pred;        /* predicted decrease 1/2 (b^T d + d^T r_pcg + lambda d^T D d) */
+  double pcg_rel_resid; /* ||r_pcg|| / ||b|| at exit */
+  int32_t accepted;
+  int32_t pcg_iters;
+} caspar_iter_record;
+
+CASPAR_API void caspar_default_solve_opts(caspar_solve_opts* opts);
+
+/* Bytes of device workspace a handle of this size needs (0 on bad sizes).
+ * n_obs must be < 2^31, n_cams < 2^25. */
+CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int precision);
+
+/* Build a problem (paper Sec. VI-A: cameras, points, observations).
+ * cams (dev) [n_cams][9] BAL; points (dev) [n_points][3]; obs_cam, obs_pt
+ * (dev) int32 [n_obs]; obs_px (dev) [n_obs][2].  workspace (dev, >= 256-byte
+ * aligned, caspar_ba_workspace_bytes() long) must outlive the handle; the
+ * library never allocates device memory of its own.  Inputs are validated
+ * (indices in range, values finite -> CASPAR_EINVAL).  The observations are
+ * reordered internally (point-major, points grouped by their least-observed
+ * camera); that order never shows at the boundary. */
+CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                     const double* cams, const double* points, const int32_t* obs_cam,
+                     const int32_t* obs_pt, const double* obs_px, int precision,
+                     void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Run Levenberg-Marquardt from the current parameters (Sec. V).  opts may be
+ * NULL (defaults).  stats (host) may be NULL; history (host) may be NULL or
+ * hold opts->max_lm_iters records.  The parameters afterwards are the last
+ * accepted ones.  Returns CASPAR_ENUMERIC if the initial cost is not finite. */
+CASPAR_API int caspar_ba_solve(caspar_ba* h, const caspar_solve_opts* opts, caspar_solve_stats* stats,
+                    caspar_iter_record* history);
+
+/* Current parameters in BAL layout, caller order (dev outputs; either may be
+ * NULL). */
+CASPAR_API int caspar_ba_get_params(caspar_ba* h, double* cams, double* points);
+
+/* Replace the parameters (dev inputs, BAL, caller order; either may be NULL
+ * to keep that part).  Use with lambda0 = the last final_lambda for a warm
+ * restart. */
+CASPAR_API int caspar_ba_set_params(caspar_ba* h, const double* cams, const double* points);
+
+/* Replace the observed pixels (dev [n_obs][2], caller order). */
+CASPAR_API int caspar_ba_set_observations(caspar_ba* h, const double* obs_px);
+
+/* Implicit adjoint of the optimum with respect to the observed pixels.
+ * With g the tangent gradient of a loss L(cameras*, points*), solve
+ * (J^T J + lambda_adj D) v = g by the same block-Jacobi PCG and write
+ * dL/dpx_o = J_o v (dev [n_obs][2], caller order), since dr/dpx = -I.
+ * grad_cams (dev [n_cams][9], BAL: gradient w.r.t. the angle-axis vector,
+ * translation, f, k1, k2; may be NULL = 0) is mapped to the right tangent
+ * with the inverse right Jacobian of SO(3); grad_points (dev [n_points][3],
+ * may be NULL = 0).  J and D are those of the current parameters.
+ * pcg_iters (host, may be NULL) receives the iteration count. */
+CASPAR_API int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points,
+                       double lambda_adj, double pcg_tol, int32_t max_pcg_iters,
+                       double* grad_obs_px, int32_t* pcg_iters);
+
+/* ---- Parity hooks: single steps of the hot path at the current parameters ---- */
+
+/* Linearise (residuals, Jacobian blocks, cost, gradient g = J^T r, damping
+ * diagonal D = clamp(diag J^T J, 1e-6, 1e32)).  cost (host) may be NULL;
+ * resid (dev [n_obs][2]), jac_cam (dev [n_obs][2][9]), jac_pt
+ * (dev [n_obs][2][3]), grad (dev [N]) and diag (dev [N]) may each be NULL.
+ * Outputs are float64 in caller order (FP32_MIXED values are widened). */
+CASPAR_API int caspar_ba_linearize(caspar_ba* h, double* cost, double* resid, double* jac_cam,
+                        double* jac_pt, double* grad, double* diag);
+
+/* w = (J^T J + lambda D) p with J, D of the last linearisation (linearises
+ * first if the parameters changed).  p, w (dev [N]); pAp (host, may be NULL)
+ * receives p^T w as accumulated by the fused kernel. */
+CASPAR_API int caspar_ba_matvec(caspar_ba* h, double lambda, const double* p, double* w, double* pAp);
+
+/* z = M^-1 r with M the block diagonal of J^T J + lambda D (dev [N]). */
+CASPAR_API int caspar_ba_block_jacobi_apply(caspar_ba* h, double lambda, const double* r, double* z);
+
+/* PCG on (J^T J + lambda D) x = b from x = 0 (dev [N]); iters and rel_resid
+ * (host, may be NULL) receive the iteration count and ||r||/||b|| of the
+ * recurrence residual. */
+CASPAR_API int caspar_ba_pcg(caspar_ba* h, double lambda, const double* b, double tol, int32_t max_iters,
+                  double* x, int32_t* iters, double* rel_resid);
+
+/* Cost F = 1/2 sum |r|^2 at the current parameters, accumulated in float64
+ * from residuals evaluated in float64 regardless of the handle's precision
+ * (host out). */
+CASPAR_API int caspar_ba_cost_fp64(caspar_ba* h, double* cost);
+
+/* Predicted pixels of the Snavely model for arbitrary parameters, float64,
+ * no handle needed (dev in/out, caller layout).  hip_stream may be NULL. */
+CASPAR_API int caspar_project(int32_t n_cams, int32_t n_points, int64_t n_obs, const double* cams,
+                   const double* points, const int32_t* obs_cam, const int32_t* obs_pt,
+                   double* px_out, void* hip_stream);
+
+/* Sizes of the internal layout (host outs, any may be NULL): the number of
+ * cameras accumulated in LDS by the fused product, observations of the other
+ * cameras, wave tiles, and workgroups of the fused product. */
+CASPAR_API int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* cold_obs, int64_t* n_tiles,
+                          int32_t* matvec_groups);
+
+CASPAR_API void caspar_ba_destroy(caspar_ba* h);
+
+/* Message of the last failed call on this thread ("" if none). */
+CASPAR_API const char* caspar_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CASPAR_BA_H */

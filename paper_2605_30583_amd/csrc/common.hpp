@@ -1,0 +1,286 @@
+// Internal declarations shared by the HIP translation units of the
+// bundle-adjustment library.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "caspar_ba.h"
+
+namespace cba {
+
+// ---------------------------------------------------------------------------
+// Errors: every public entry point catches Error and maps it to a status.
+// ---------------------------------------------------------------------------
+struct Error {
+  int status;
+  std::string msg;
+};
+
+void set_last_error(const std::string& msg);
+[[noreturn]] void fail(int status, const std::string& msg);
+
+#define CBA_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      ::cba::fail(CASPAR_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CBA_REQUIRE(cond, msg)                          \
+  do {                                                  \
+    if (!(cond)) ::cba::fail(CASPAR_EINVAL, (msg));     \
+  } while (0)
+
+// Checks the launch status of the kernel just enqueued.
+#define CBA_LAUNCHED() CBA_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Sizes and layout constants.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kTileMax = 64;         // observations per wave tile
+constexpr int kCamStride = 16;       // doubles per camera row: R(9) t(3) f k1 k2 pad
+constexpr int kCamChunk = 2048;      // camera-major entries per linearisation chunk
+constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
+constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
+constexpr int kMvThreads = 1024;     // fused product: 16 waves per workgroup
+constexpr int kMvWaves = kMvThreads / kWave;
+constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
+constexpr int kMaxHot = kLdsBudget / (9 * 8);
+constexpr int kMaxPartials = 4096;   // per-workgroup partial slots
+constexpr int kPartialWidth = 4;     // doubles per partial slot
+constexpr int kCamBits = 25;         // meta: camera id bits; local point in bits 25..30
+constexpr int kNumCUs = 256;
+
+// Wave tile: a run of whole points (or one slice of a point with more than
+// kTileMax observations) covering <= kTileMax consecutive observations.
+struct Tile {
+  int obs_begin;   // first observation (internal order)
+  int pt_begin;    // first point (internal order)
+  int cold_begin;  // first row in the cold-camera row buffer
+  int split_row;   // row in the split-point buffer, -1 for ordinary tiles
+  int info;        // n_obs | n_pts << 7 | seg_steps << 14 | split << 17 | first slice << 18
+  int pad0, pad1, pad2;
+};
+static_assert(sizeof(Tile) == 32, "tile is two dwordx4");
+
+__host__ __device__ inline int tile_nobs(int info) { return info & 127; }
+__host__ __device__ inline int tile_npts(int info) { return (info >> 7) & 127; }
+__host__ __device__ inline int tile_steps(int info) { return (info >> 14) & 7; }
+__host__ __device__ inline bool tile_split(int info) { return (info >> 17) & 1; }
+__host__ __device__ inline bool tile_first(int info) { return (info >> 18) & 1; }
+
+// Camera-major linearisation chunk: entries [begin, end) of camera cam.
+struct Chunk {
+  int cam, begin, end, pad;
+};
+
+// Points observed more than kTileMax times: their tiles' partial rows.
+struct SplitPoint {
+  int pt, row_begin, nrows, pad;
+};
+
+// PCG / reduction scalars living on the device.
+struct DevScalars {
+  double pAp, alpha, rho, rr, bb, tol2, beta, pad0;
+  int iter, done, reason, max_iter;
+  double red[8];
+  int err;
+  int pad1[3];
+};
+enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXITER = 3, PCG_ZERO_RHS = 4 };
+
+// ---------------------------------------------------------------------------
+// The handle.
+// ---------------------------------------------------------------------------
+struct Vectors {
+  void* g;  // gradient J^T r
+  void* D;  // damping diagonal
+  void* x;
+  void* r;
+  void* z;
+  void* p;
+  void* w;
+  void* v;  // scratch vector (hooks, adjoint right-hand side)
+};
+
+}  // namespace cba
+
+struct caspar_ba {
+  int nc = 0, np = 0;
+  int no = 0;
+  int prec = CASPAR_FP64;
+  int N = 0;              // 9 nc + 3 np
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // layout
+  int K = 0;              // cameras accumulated in LDS (internal ids < K)
+  int G = 0;              // workgroups of the fused product
+  int n_tiles = 0;
+  int n_cold = 0;         // observations of cameras >= K
+  int n_split_tiles = 0;
+  int n_split_pts = 0;
+  int n_orphan_pts = 0;   // points without observations (internal ids [0, n_orphan))
+  int n_chunks = 0;
+  int no_pad = 0;         // observations rounded up to 64
+
+  // parameters (float64, internal order)
+  double* cam = nullptr;        // [nc][16]
+  double* cam_trial = nullptr;
+  double* X = nullptr;          // [np][3]
+  double* X_trial = nullptr;
+
+  // permutations
+  int* cam_c2i = nullptr;
+  int* cam_i2c = nullptr;
+  int* pt_c2i = nullptr;
+  int* pt_i2c = nullptr;
+  int* obs_s2c = nullptr;       // internal observation -> caller index
+
+  // point-major observation data
+  uint32_t* meta = nullptr;     // cam | local point << 25
+  double* px = nullptr;         // [no][2]
+  void* J = nullptr;            // 12 columns x 2 rows, 16-byte chunks, chunk-major
+  cba::Tile* tiles = nullptr;
+
+  // camera-major data
+  int* cm_obs = nullptr;        // [no] internal observation of each camera-major entry
+  int* cm_pt = nullptr;         // [no] internal point of each camera-major entry
+  double* cm_px = nullptr;      // [no][2]
+  int* cam_off = nullptr;       // [nc + 1]
+  cba::Chunk* chunks = nullptr;
+  int* chunk_off = nullptr;     // [nc + 1] chunks of camera c
+  double* chunk_rows = nullptr; // [n_chunks][54]
+
+  // fused product side buffers
+  int* cold_list = nullptr;     // cold rows grouped by camera
+  int* cold_off = nullptr;      // [nc - K + 1]
+  double* cold_rows = nullptr;  // [n_cold][9]
+  cba::SplitPoint* split_pts = nullptr;
+  double* split_rows = nullptr; // [n_split_tiles][9]
+  double* hot_rows = nullptr;   // [G][K][9]
+
+  // normal-equation blocks
+  double* Hcc = nullptr;        // [nc][45]
+  double* Hpp = nullptr;        // [np][6]
+  void* Mc = nullptr;           // [nc][45] inverse blocks (precision)
+  void* Mp = nullptr;           // [np][6]
+  cba::Vectors vec;
+
+  double* partials = nullptr;   // [kMaxPartials][4]
+  cba::DevScalars* scal = nullptr;
+
+  // state
+  bool linearized = false;      // J, g, D, H match the current parameters
+  double cost = 0.0;            // F at the current parameters (valid if linearized)
+  double gmax = 0.0;
+  double bj_lambda = -1.0;      // lambda of the stored block-Jacobi inverse
+};
+
+namespace cba {
+
+// Arena planning: byte offsets of every region inside the caller workspace.
+struct Plan {
+  size_t total = 0;
+  struct Region {
+    size_t off = 0, bytes = 0;
+  };
+  Region cam, cam_trial, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+      tiles, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
+      split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal;
+  size_t vec_bytes = 0;
+  int K = 0, G = 0;
+  size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;
+};
+bool make_plan(int nc, int np, int64_t no, int prec, Plan& plan);
+
+inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
+
+// Launch helpers implemented per translation unit (S = double or float).
+// layout.hip
+void upload_cameras_bal(caspar_ba* h, const double* cams_bal_caller, double* cam_internal);
+void upload_points(caspar_ba* h, const double* pts_caller, double* X_internal);
+// linearize.hip
+void run_linearize(caspar_ba* h);                   // J, g, H, D, cost, gmax
+double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  // F at params
+void run_retract(caspar_ba* h, const void* delta);  // trial = current (+) delta
+void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* jp);
+// matvec.hip
+void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool scalar_alpha);
+// pcg.hip
+void run_block_jacobi(caspar_ba* h, double lambda);
+void run_bj_apply(caspar_ba* h, const void* r, void* z);
+int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double tol, int max_iters,
+            int check_every, void* x, double* rel_resid);
+double run_dot(caspar_ba* h, const void* a, const void* b, const void* wdiag);  // sum a b (w)
+double run_absmax(caspar_ba* h, const void* a);
+void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
+void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);
+void run_zero(caspar_ba* h, void* v, size_t count_scalars);
+// helpers
+void sync(caspar_ba* h);
+DevScalars read_scalars(caspar_ba* h);
+
+}  // namespace cba
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+namespace cba {
+
+template <typename T>
+struct Scalar;
+template <>
+struct Scalar<double> {
+  static constexpr double eps() { return 10.0 * 2.220446049250313e-16; }
+};
+template <>
+struct Scalar<float> {
+  static constexpr float eps() { return 10.0f * 1.1920928955078125e-07f; }
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  `lds` holds one
+// double per wave.  Contains barriers: call from all threads.
+__device__ inline double block_sum(double v, double* lds) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += lds[i];
+  return s;
+}
+
+__device__ inline double block_max(double v, double* lds) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s = fmax(s, lds[i]);
+  return s;
+}
+
+}  // namespace cba

@@ -1,0 +1,764 @@
+// Problem set-up: arena planning, input validation, the observation ordering
+// and index tables built once at create time, parameter and observation I/O,
+// and the stand-alone projection.
+//
+// Ordering (built on the GPU with radix sorts, small tables on the host):
+//  * cameras are relabelled by observation count, most observed first; the
+//    first K of them are accumulated in LDS by the fused product;
+//  * points are grouped by their least-observed camera (largest internal
+//    camera id), so that observations of rarely seen cameras sit together;
+//  * observations are sorted point-major (camera, then caller index, inside
+//    a point) and cut into wave tiles of <= 64 observations holding whole
+//    points (points seen more than 64 times get tiles of their own);
+//  * a camera-major index over the same observations drives the per-camera
+//    block sums.
+// This is the role the paper's sorted block-unique index structure plays for
+// its shared gather / scatter accessors (Section IV-A), laid out for 64-wide
+// wavefronts.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.hpp"
+#include "model.hpp"
+
+namespace cba {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+static int ceil_log2(long long v) {
+  int b = 0;
+  while ((1LL << b) < v) ++b;
+  return b;
+}
+
+static size_t sort_temp_bytes(int64_t no) {
+  size_t a = 0, b = 0;
+  if (no > 0) {
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, (int)no, 0, 64) !=
+            hipSuccess ||
+        hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, (int)no, 0, 32) !=
+            hipSuccess)
+      return (size_t)-1;
+  }
+  return std::max(a, b) + (1 << 20);
+}
+
+static int groups_per_cu(int K) {
+  const size_t lds = (size_t)K * 9 * sizeof(double);
+  return lds > 80 * 1024 ? 1 : 2;
+}
+
+bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
+  if (nc < 0 || np < 0 || no < 0) return false;
+  if (no >= (int64_t)1 << 31 || nc >= (1 << kCamBits)) return false;
+  if (prec != CASPAR_FP64 && prec != CASPAR_FP32_MIXED) return false;
+  if (no > 0 && (nc == 0 || np == 0)) return false;
+  if ((int64_t)9 * nc + 3 * (int64_t)np >= ((int64_t)1 << 31)) return false;
+  const size_t s = scalar_bytes(prec);
+  const size_t nch = prec == CASPAR_FP64 ? 12 : 6;
+  const size_t sort_bytes = sort_temp_bytes(no);
+  if (sort_bytes == (size_t)-1) return false;
+  const size_t no_pad = align_up((size_t)no, 64);
+  const size_t N = 9 * (size_t)nc + 3 * (size_t)np;
+  p = Plan{};
+  p.K = std::min(nc, kMaxHot);
+  p.G = groups_per_cu(p.K) * kNumCUs;
+  p.max_tiles = (size_t)no / 16 + 8;
+  p.max_chunks = (size_t)no / kCamChunk + nc + 1;
+  p.max_cold = nc > p.K ? (size_t)((no * (int64_t)(nc - p.K)) / nc + 1) : 0;
+  p.max_split_tiles = (size_t)no / 32 + 2;
+  p.max_split_pts = (size_t)no / 65 + 1;
+
+  size_t off = 0;
+  auto take = [&](Plan::Region& r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += align_up(bytes);
+  };
+  take(p.scal, sizeof(DevScalars));
+  take(p.partials, (size_t)kMaxPartials * kPartialWidth * 8);
+  take(p.cam, (size_t)nc * kCamStride * 8);
+  take(p.cam_trial, (size_t)nc * kCamStride * 8);
+  take(p.X, (size_t)np * 3 * 8);
+  take(p.X_trial, (size_t)np * 3 * 8);
+  take(p.cam_c2i, (size_t)nc * 4);
+  take(p.cam_i2c, (size_t)nc * 4);
+  take(p.pt_c2i, (size_t)np * 4);
+  take(p.pt_i2c, (size_t)np * 4);
+  take(p.obs_s2c, (size_t)no * 4);
+  take(p.meta, no_pad * 4);
+  take(p.px, (size_t)no * 16);
+  // J doubles as the create-time scratch (sort buffers, counters).
+  const size_t scratch = 2 * 8 * (size_t)no + 2 * 4 * (size_t)no + 4 * (size_t)no +
+                         align_up(sort_bytes) + 8 * (size_t)np + 8 * (size_t)nc + 8192;
+  take(p.J, std::max(nch * no_pad * 16, scratch));
+  take(p.tiles, p.max_tiles * sizeof(Tile));
+  take(p.cm_pt, (size_t)no * 4);
+  take(p.cm_px, (size_t)no * 16);
+  take(p.cam_off, ((size_t)nc + 1) * 4);
+  take(p.chunks, p.max_chunks * sizeof(Chunk));
+  take(p.chunk_off, ((size_t)nc + 1) * 4);
+  take(p.chunk_rows, p.max_chunks * kCamRowWidth * 8);
+  take(p.cold_list, p.max_cold * 4 + 4);
+  take(p.cold_off, ((size_t)(nc - p.K) + 1) * 4);
+  take(p.cold_rows, p.max_cold * 9 * 8 + 8);
+  take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
+  take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
+  take(p.hot_rows, (size_t)p.G * p.K * 9 * 8);
+  take(p.Hcc, (size_t)nc * 45 * 8);
+  take(p.Hpp, (size_t)np * 6 * 8);
+  take(p.Mc, (size_t)nc * 45 * s);
+  take(p.Mp, (size_t)np * 6 * s);
+  p.vec_bytes = align_up(std::max<size_t>(N, 1) * s);
+  take(p.vecs, 8 * p.vec_bytes);
+  take(p.cm_obs, (size_t)no * 4);
+  p.total = off;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels used at create time.
+// ---------------------------------------------------------------------------
+__global__ void k_validate(int nc, int np, int no, const double* __restrict__ cams,
+                           const double* __restrict__ pts, const int* __restrict__ oc,
+                           const int* __restrict__ op, const double* __restrict__ px,
+                           DevScalars* sc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int err = 0;
+  if (i < no) {
+    const int c = oc[i], p = op[i];
+    if (c < 0 || c >= nc || p < 0 || p >= np) err |= 1;
+    if (!isfinite(px[2 * i]) || !isfinite(px[2 * i + 1])) err |= 2;
+  }
+  if (i < (int64_t)nc * 9 && !isfinite(cams[i])) err |= 4;
+  if (i < (int64_t)np * 3 && !isfinite(pts[i])) err |= 8;
+  if (err) atomicOr(&sc->err, err);
+}
+
+__global__ void k_count(int no, const int* __restrict__ oc, const int* __restrict__ op,
+                        int* cam_cnt, int* pt_cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < no) {
+    atomicAdd(&cam_cnt[oc[i]], 1);
+    atomicAdd(&pt_cnt[op[i]], 1);
+  }
+}
+
+__global__ void k_point_key(int no, const int* __restrict__ oc, const int* __restrict__ op,
+                            const int* __restrict__ cam_c2i, int* pt_key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < no) atomicMax(&pt_key[op[i]], cam_c2i[oc[i]]);
+}
+
+__global__ void k_make_keys(int no, const int* __restrict__ oc, const int* __restrict__ op,
+                            const int* __restrict__ cam_c2i, const int* __restrict__ pt_c2i,
+                            uint64_t* keys, int* vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < no) {
+    keys[i] = ((uint64_t)(uint32_t)pt_c2i[op[i]] << kCamBits) | (uint64_t)(uint32_t)cam_c2i[oc[i]];
+    vals[i] = i;
+  }
+}
+
+// One wave per tile: meta word, sorted pixels, camera keys for the
+// camera-major sort.
+__global__ void k_fill_obs(int n_tiles, const Tile* __restrict__ tiles,
+                           const uint64_t* __restrict__ skeys, const int* __restrict__ s2c,
+                           const double* __restrict__ px_caller, uint32_t* meta, double* px,
+                           uint32_t* cam_keys, int* cam_vals) {
+  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (t >= n_tiles) return;
+  const Tile tl = tiles[t];
+  const int n = tile_nobs(tl.info);
+  if (lane >= n) return;
+  const int s = tl.obs_begin + lane;
+  const uint64_t key = skeys[s];
+  const int ci = (int)(key & ((1u << kCamBits) - 1));
+  const int pi = (int)(key >> kCamBits);
+  meta[s] = (uint32_t)ci | ((uint32_t)(pi - tl.pt_begin) << kCamBits);
+  const int c = s2c[s];
+  px[2 * s] = px_caller[2 * (size_t)c];
+  px[2 * s + 1] = px_caller[2 * (size_t)c + 1];
+  cam_keys[s] = (uint32_t)ci;
+  cam_vals[s] = s;
+}
+
+__global__ void k_fill_cm(int no, const int* __restrict__ cm_obs, const uint64_t* __restrict__ skeys,
+                          const double* __restrict__ px, int* cm_pt, double* cm_px) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < no) {
+    const int s = cm_obs[j];
+    cm_pt[j] = (int)(skeys[s] >> kCamBits);
+    cm_px[2 * j] = px[2 * s];
+    cm_px[2 * j + 1] = px[2 * s + 1];
+  }
+}
+
+// Cold observations (camera id >= K) per tile.
+__global__ void k_cold_count(int n_tiles, int K, const Tile* __restrict__ tiles,
+                             const uint32_t* __restrict__ meta, int* cnt) {
+  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (t >= n_tiles) return;
+  const Tile tl = tiles[t];
+  const bool cold = lane < tile_nobs(tl.info) &&
+                    (int)(meta[tl.obs_begin + lane] & ((1u << kCamBits) - 1)) >= K;
+  const unsigned long long m = __ballot(cold);
+  if (lane == 0) cnt[t] = __popcll(m);
+}
+
+// Row of each cold observation: tile base + rank among the tile's cold lanes.
+__global__ void k_cold_rows(int n_tiles, int K, const Tile* __restrict__ tiles,
+                            const uint32_t* __restrict__ meta, int* row_of) {
+  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (t >= n_tiles) return;
+  const Tile tl = tiles[t];
+  const bool act = lane < tile_nobs(tl.info);
+  const bool cold = act && (int)(meta[tl.obs_begin + lane] & ((1u << kCamBits) - 1)) >= K;
+  const unsigned long long m = __ballot(cold);
+  const int rank = __popcll(m & ((1ull << lane) - 1ull));
+  if (act) row_of[tl.obs_begin + lane] = cold ? tl.cold_begin + rank : -1;
+}
+
+__global__ void k_cold_list(int n, int base, const int* __restrict__ cm_obs,
+                            const int* __restrict__ row_of, int* cold_list) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) cold_list[j] = row_of[cm_obs[base + j]];
+}
+
+__global__ void k_cams_from_bal(int nc, const double* __restrict__ bal, const int* __restrict__ c2i,
+                                double* cam) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double* b = bal + 9 * (size_t)c;
+  double* o = cam + (size_t)c2i[c] * kCamStride;
+  double R[9];
+  so3_exp(b[0], b[1], b[2], R);
+  for (int i = 0; i < 9; ++i) o[i] = R[i];
+  for (int i = 0; i < 6; ++i) o[9 + i] = b[3 + i];
+  o[15] = 0.0;
+}
+
+__global__ void k_cams_to_bal(int nc, const double* __restrict__ cam, const int* __restrict__ c2i,
+                              double* bal) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double* in = cam + (size_t)c2i[c] * kCamStride;
+  double R[9], w[3];
+  for (int i = 0; i < 9; ++i) R[i] = in[i];
+  so3_log(R, w);
+  double* o = bal + 9 * (size_t)c;
+  o[0] = w[0];
+  o[1] = w[1];
+  o[2] = w[2];
+  for (int i = 0; i < 6; ++i) o[3 + i] = in[9 + i];
+}
+
+__global__ void k_points_in(int np, const double* __restrict__ in, const int* __restrict__ c2i,
+                            double* X) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int q = c2i[p];
+  for (int k = 0; k < 3; ++k) X[3 * (size_t)q + k] = in[3 * (size_t)p + k];
+}
+
+__global__ void k_points_out(int np, const double* __restrict__ X, const int* __restrict__ c2i,
+                             double* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int q = c2i[p];
+  for (int k = 0; k < 3; ++k) out[3 * (size_t)p + k] = X[3 * (size_t)q + k];
+}
+
+__global__ void k_set_px(int no, const int* __restrict__ s2c, const double* __restrict__ px_caller,
+                         double* px) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < no) {
+    const size_t c = s2c[s];
+    px[2 * s] = px_caller[2 * c];
+    px[2 * s + 1] = px_caller[2 * c + 1];
+  }
+}
+
+__global__ void k_set_cm_px(int no, const int* __restrict__ cm_obs, const double* __restrict__ px,
+                            double* cm_px) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < no) {
+    const int s = cm_obs[j];
+    cm_px[2 * j] = px[2 * s];
+    cm_px[2 * j + 1] = px[2 * s + 1];
+  }
+}
+
+__global__ void k_project(int64_t no, const double* __restrict__ cams, const double* __restrict__ pts,
+                          const int* __restrict__ oc, const int* __restrict__ op, double* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= no) return;
+  const double* b = cams + 9 * (size_t)oc[i];
+  Cam<double> c;
+  so3_exp(b[0], b[1], b[2], c.R);
+  c.t[0] = b[3];
+  c.t[1] = b[4];
+  c.t[2] = b[5];
+  c.f = b[6];
+  c.k1 = b[7];
+  c.k2 = b[8];
+  const double* X = pts + 3 * (size_t)op[i];
+  double u0, u1;
+  snavely_residual<double>(c, X[0], X[1], X[2], 0.0, 0.0, u0, u1);
+  out[2 * i] = u0;
+  out[2 * i + 1] = u1;
+}
+
+static inline unsigned blocks_for(int64_t n, int threads) {
+  return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+void sync(caspar_ba* h) { CBA_HIP(hipStreamSynchronize(h->stream)); }
+
+DevScalars read_scalars(caspar_ba* h) {
+  DevScalars s;
+  CBA_HIP(hipMemcpyAsync(&s, h->scal, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+  return s;
+}
+
+void upload_cameras_bal(caspar_ba* h, const double* bal, double* cam) {
+  if (h->nc == 0) return;
+  k_cams_from_bal<<<blocks_for(h->nc, 256), 256, 0, h->stream>>>(h->nc, bal, h->cam_c2i, cam);
+  CBA_LAUNCHED();
+}
+
+void upload_points(caspar_ba* h, const double* pts, double* X) {
+  if (h->np == 0) return;
+  k_points_in<<<blocks_for(h->np, 256), 256, 0, h->stream>>>(h->np, pts, h->pt_c2i, X);
+  CBA_LAUNCHED();
+}
+
+template <typename V>
+static void h2d(caspar_ba* h, V* dst, const std::vector<V>& src) {
+  if (src.empty()) return;
+  CBA_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice, h->stream));
+  sync(h);  // the host vector may change or die right after
+}
+
+template <typename V>
+static std::vector<V> d2h(caspar_ba* h, const V* src, size_t n) {
+  std::vector<V> out(n);
+  if (n) {
+    CBA_HIP(hipMemcpyAsync(out.data(), src, n * sizeof(V), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  }
+  return out;
+}
+
+static void build_layout(caspar_ba* h, const double* cams, const double* pts, const int* oc,
+                         const int* op, const double* px_caller, char* ws, const Plan& plan) {
+  const int nc = h->nc, np = h->np, no = h->no;
+  hipStream_t st = h->stream;
+
+  // Create-time scratch inside the J region.
+  char* scratch = (char*)h->J;
+  size_t so = 0;
+  auto carve = [&](size_t bytes) {
+    char* p = scratch + so;
+    so += align_up(bytes);
+    return (void*)p;
+  };
+  uint64_t* keys_a = (uint64_t*)carve(8 * (size_t)no);
+  uint64_t* keys_b = (uint64_t*)carve(8 * (size_t)no);
+  int* vals_a = (int*)carve(4 * (size_t)no);
+  int* vals_b = (int*)carve(4 * (size_t)no);
+  int* row_of = (int*)carve(4 * (size_t)no);
+  const size_t cub_bytes = sort_temp_bytes(no);
+  void* cub_tmp = carve(cub_bytes);
+  int* pt_cnt = (int*)carve(4 * (size_t)np);
+  int* pt_key = (int*)carve(4 * (size_t)np);
+  int* cam_cnt = (int*)carve(4 * (size_t)nc);
+  if (so > plan.J.bytes) fail(CASPAR_ENOMEM, "internal: create scratch exceeds plan");
+  int* cm_obs = h->cm_obs;
+
+  // Validation.
+  CBA_HIP(hipMemsetAsync(h->scal, 0, sizeof(DevScalars), st));
+  {
+    const int64_t n = std::max<int64_t>({(int64_t)no, (int64_t)nc * 9, (int64_t)np * 3, 1});
+    k_validate<<<blocks_for(n, 256), 256, 0, st>>>(nc, np, no, cams, pts, oc, op, px_caller, h->scal);
+    CBA_LAUNCHED();
+    const DevScalars s = read_scalars(h);
+    if (s.err & 1) fail(CASPAR_EINVAL, "observation camera or point index out of range");
+    if (s.err & 2) fail(CASPAR_EINVAL, "non-finite observed pixel");
+    if (s.err & 4) fail(CASPAR_EINVAL, "non-finite camera parameter");
+    if (s.err & 8) fail(CASPAR_EINVAL, "non-finite point coordinate");
+  }
+
+  // Camera relabelling by observation count.
+  if (nc) CBA_HIP(hipMemsetAsync(cam_cnt, 0, 4 * (size_t)nc, st));
+  if (np) CBA_HIP(hipMemsetAsync(pt_cnt, 0, 4 * (size_t)np, st));
+  if (no) {
+    k_count<<<blocks_for(no, 256), 256, 0, st>>>(no, oc, op, cam_cnt, pt_cnt);
+    CBA_LAUNCHED();
+  }
+  std::vector<int> ccnt = d2h(h, cam_cnt, nc);
+  std::vector<int> cam_i2c(nc), cam_c2i(nc);
+  std::iota(cam_i2c.begin(), cam_i2c.end(), 0);
+  std::stable_sort(cam_i2c.begin(), cam_i2c.end(), [&](int a, int b) { return ccnt[a] > ccnt[b]; });
+  for (int i = 0; i < nc; ++i) cam_c2i[cam_i2c[i]] = i;
+  h2d(h, h->cam_c2i, cam_c2i);
+  h2d(h, h->cam_i2c, cam_i2c);
+
+  // Point order: by least-observed camera (largest internal id), then id.
+  if (np) CBA_HIP(hipMemsetAsync(pt_key, 0xff, 4 * (size_t)np, st));  // -1
+  if (no) {
+    k_point_key<<<blocks_for(no, 256), 256, 0, st>>>(no, oc, op, h->cam_c2i, pt_key);
+    CBA_LAUNCHED();
+  }
+  std::vector<int> pkey = d2h(h, pt_key, np);
+  std::vector<int> pcnt = d2h(h, pt_cnt, np);
+  std::vector<int> pt_i2c(np), pt_c2i(np);
+  {
+    std::vector<int> bucket(nc + 2, 0);
+    for (int p = 0; p < np; ++p) bucket[pkey[p] + 2]++;
+    for (int i = 1; i < nc + 2; ++i) bucket[i] += bucket[i - 1];
+    for (int p = 0; p < np; ++p) pt_i2c[bucket[pkey[p] + 1]++] = p;
+    for (int i = 0; i < np; ++i) pt_c2i[pt_i2c[i]] = i;
+  }
+  h2d(h, h->pt_c2i, pt_c2i);
+  h2d(h, h->pt_i2c, pt_i2c);
+  int n_orphan = 0;
+  while (n_orphan < np && pcnt[pt_i2c[n_orphan]] == 0) ++n_orphan;
+  h->n_orphan_pts = n_orphan;
+
+  // Wave tiles (greedy packing of whole points) and split points.
+  std::vector<Tile> tiles;
+  std::vector<SplitPoint> splits;
+  {
+    int64_t off = 0;
+    Tile cur{};
+    int cur_n = 0, cur_pts = 0, cur_max = 0;
+    auto steps = [](int m) { return m <= 1 ? 0 : ceil_log2(m); };
+    auto flush = [&]() {
+      if (cur_n == 0) return;
+      cur.info = cur_n | (cur_pts << 7) | (steps(cur_max) << 14);
+      cur.split_row = -1;
+      tiles.push_back(cur);
+      cur_n = cur_pts = cur_max = 0;
+    };
+    int split_row = 0;
+    for (int i = n_orphan; i < np; ++i) {
+      const int k = pcnt[pt_i2c[i]];
+      if (k > kTileMax) {
+        flush();
+        SplitPoint sp{i, split_row, 0, 0};
+        for (int s0 = 0; s0 < k; s0 += kTileMax) {
+          Tile t{};
+          const int n = std::min(kTileMax, k - s0);
+          t.obs_begin = (int)(off + s0);
+          t.pt_begin = i;
+          t.split_row = split_row++;
+          t.info = n | (1 << 7) | (steps(n) << 14) | (1 << 17) | ((s0 == 0 ? 1 : 0) << 18);
+          tiles.push_back(t);
+          sp.nrows++;
+        }
+        splits.push_back(sp);
+      } else {
+        if (cur_n + k > kTileMax) flush();
+        if (cur_n == 0) {
+          cur = Tile{};
+          cur.obs_begin = (int)off;
+          cur.pt_begin = i;
+        }
+        cur_n += k;
+        cur_pts += 1;
+        cur_max = std::max(cur_max, k);
+      }
+      off += k;
+    }
+    flush();
+    if (off != no) fail(CASPAR_EINVAL, "internal: observation count mismatch");
+  }
+  if (tiles.size() > plan.max_tiles || splits.size() > plan.max_split_pts)
+    fail(CASPAR_ENOMEM, "internal: tile table exceeds plan");
+  h->n_tiles = (int)tiles.size();
+  h->n_split_pts = (int)splits.size();
+  h->n_split_tiles = splits.empty() ? 0 : splits.back().row_begin + splits.back().nrows;
+  if ((size_t)h->n_split_tiles > plan.max_split_tiles) fail(CASPAR_ENOMEM, "internal: split rows");
+  h2d(h, h->split_pts, splits);
+
+  // Point-major sort of the observations.
+  const int pt_bits = std::max(1, ceil_log2((long long)np + 1));
+  const int cam_bits = std::max(1, ceil_log2((long long)nc + 1));
+  if (no) {
+    k_make_keys<<<blocks_for(no, 256), 256, 0, st>>>(no, oc, op, h->cam_c2i, h->pt_c2i, keys_a, vals_a);
+    CBA_LAUNCHED();
+    size_t tb = cub_bytes;
+    CBA_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, tb, keys_a, keys_b, vals_a, h->obs_s2c, no, 0,
+                                               kCamBits + pt_bits, st));
+    h2d(h, h->tiles, tiles);
+    k_fill_obs<<<blocks_for((int64_t)h->n_tiles * kWave, 256), 256, 0, st>>>(
+        h->n_tiles, h->tiles, keys_b, h->obs_s2c, px_caller, h->meta, h->px, (uint32_t*)keys_a,
+        vals_a);
+    CBA_LAUNCHED();
+    // Camera-major order (stable: inside a camera, point order).
+    tb = cub_bytes;
+    CBA_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, tb, (const uint32_t*)keys_a, (uint32_t*)vals_b,
+                                               vals_a, cm_obs, no, 0, cam_bits, st));
+    k_fill_cm<<<blocks_for(no, 256), 256, 0, st>>>(no, cm_obs, keys_b, h->px, h->cm_pt, h->cm_px);
+    CBA_LAUNCHED();
+  }
+
+  // Camera offsets (internal order) and linearisation chunks.
+  std::vector<int> cam_off(nc + 1, 0), chunk_off(nc + 1, 0);
+  std::vector<Chunk> chunks;
+  for (int i = 0; i < nc; ++i) {
+    const int n = ccnt[cam_i2c[i]];
+    cam_off[i + 1] = cam_off[i] + n;
+    for (int b = 0; b < n; b += kCamChunk)
+      chunks.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + std::min(n, b + kCamChunk), 0});
+    chunk_off[i + 1] = (int)chunks.size();
+  }
+  if (chunks.size() > plan.max_chunks) fail(CASPAR_ENOMEM, "internal: chunk table exceeds plan");
+  h->n_chunks = (int)chunks.size();
+  h2d(h, h->cam_off, cam_off);
+  h2d(h, h->chunk_off, chunk_off);
+  h2d(h, h->chunks, chunks);
+
+  // Cold cameras: rows of the fused product and their per-camera lists.
+  h->n_cold = (nc > h->K) ? cam_off[nc] - cam_off[h->K] : 0;
+  if ((size_t)h->n_cold > plan.max_cold) fail(CASPAR_ENOMEM, "internal: cold rows exceed plan");
+  if (h->n_cold > 0) {
+    int* cnt = row_of;  // reuse as per-tile counter first
+    k_cold_count<<<blocks_for((int64_t)h->n_tiles * kWave, 256), 256, 0, st>>>(h->n_tiles, h->K, h->tiles,
+                                                                           h->meta, cnt);
+    CBA_LAUNCHED();
+    std::vector<int> tc = d2h(h, cnt, h->n_tiles);
+    int run = 0;
+    for (int t = 0; t < h->n_tiles; ++t) {
+      tiles[t].cold_begin = run;
+      run += tc[t];
+    }
+    if (run != h->n_cold) fail(CASPAR_EINVAL, "internal: cold count mismatch");
+    h2d(h, h->tiles, tiles);
+    k_cold_rows<<<blocks_for((int64_t)h->n_tiles * kWave, 256), 256, 0, st>>>(h->n_tiles, h->K, h->tiles,
+                                                                          h->meta, row_of);
+    CBA_LAUNCHED();
+    k_cold_list<<<blocks_for(h->n_cold, 256), 256, 0, st>>>(h->n_cold, cam_off[h->K], cm_obs, row_of,
+                                                            h->cold_list);
+    CBA_LAUNCHED();
+    std::vector<int> coff(nc - h->K + 1);
+    for (int c = h->K; c <= nc; ++c) coff[c - h->K] = cam_off[c] - cam_off[h->K];
+    h2d(h, h->cold_off, coff);
+  } else if (no) {
+    h2d(h, h->tiles, tiles);
+  }
+
+  // Fused-product grid.
+  h->G = std::max(1, std::min(groups_per_cu(h->K) * kNumCUs, (h->n_tiles + kMvWaves - 1) / kMvWaves));
+
+  // Parameters.
+  upload_cameras_bal(h, cams, h->cam);
+  upload_points(h, pts, h->X);
+  sync(h);
+}
+
+}  // namespace cba
+
+using namespace cba;
+
+#define CBA_API_BEGIN try {
+#define CBA_API_END                  \
+  }                                  \
+  catch (const Error& e) {           \
+    set_last_error(e.msg);           \
+    return e.status;                 \
+  }                                  \
+  catch (const std::exception& e) {  \
+    set_last_error(e.what());        \
+    return CASPAR_EHIP;              \
+  }                                  \
+  set_last_error("");                \
+  return CASPAR_OK;
+
+extern "C" {
+
+const char* caspar_last_error(void) { return g_last_error.c_str(); }
+
+void caspar_default_solve_opts(caspar_solve_opts* o) {
+  if (!o) return;
+  o->lambda0 = 1e-2;
+  o->pcg_tol = 1e-3;
+  o->max_lm_iters = 20;
+  o->max_pcg_iters = 500;
+  o->lambda_min = 1e-12;
+  o->lambda_max = 1e16;
+  o->grad_tol = 1e-12;
+  o->min_cost = 1e-30;
+  o->pcg_check_every = 4;
+  o->flags = 0;
+}
+
+size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int precision) {
+  Plan p;
+  if (!make_plan(n_cams, n_points, n_obs, precision, p)) return 0;
+  return p.total;
+}
+
+int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                     const double* cams, const double* points, const int32_t* obs_cam,
+                     const int32_t* obs_pt, const double* obs_px, int precision, void* workspace,
+                     size_t workspace_bytes, void* hip_stream) {
+  caspar_ba* h = nullptr;
+  try {
+    CBA_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    Plan plan;
+    CBA_REQUIRE(make_plan(n_cams, n_points, n_obs, precision, plan),
+                "bad sizes or precision (n_obs < 2^31, n_cams < 2^25, observations need cameras and points)");
+    if (workspace_bytes < plan.total)
+      fail(CASPAR_ENOMEM, "workspace too small: need " + std::to_string(plan.total) + " bytes");
+    CBA_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+                "workspace must be non-NULL and 256-byte aligned");
+    CBA_REQUIRE(n_obs == 0 || (obs_cam && obs_pt && obs_px), "observation arrays are NULL");
+    CBA_REQUIRE(n_cams == 0 || cams, "cams is NULL");
+    CBA_REQUIRE(n_points == 0 || points, "points is NULL");
+    h = new caspar_ba();
+    h->nc = n_cams;
+    h->np = n_points;
+    h->no = (int)n_obs;
+    h->prec = precision;
+    h->N = 9 * n_cams + 3 * n_points;
+    h->stream = (hipStream_t)hip_stream;
+    h->no_pad = (int)align_up((size_t)n_obs, 64);
+    h->K = plan.K;
+    CBA_HIP(hipGetDevice(&h->device));
+    char* ws = (char*)workspace;
+    h->scal = (DevScalars*)(ws + plan.scal.off);
+    h->partials = (double*)(ws + plan.partials.off);
+    h->cam = (double*)(ws + plan.cam.off);
+    h->cam_trial = (double*)(ws + plan.cam_trial.off);
+    h->X = (double*)(ws + plan.X.off);
+    h->X_trial = (double*)(ws + plan.X_trial.off);
+    h->cam_c2i = (int*)(ws + plan.cam_c2i.off);
+    h->cam_i2c = (int*)(ws + plan.cam_i2c.off);
+    h->pt_c2i = (int*)(ws + plan.pt_c2i.off);
+    h->pt_i2c = (int*)(ws + plan.pt_i2c.off);
+    h->obs_s2c = (int*)(ws + plan.obs_s2c.off);
+    h->meta = (uint32_t*)(ws + plan.meta.off);
+    h->px = (double*)(ws + plan.px.off);
+    h->J = ws + plan.J.off;
+    h->tiles = (Tile*)(ws + plan.tiles.off);
+    h->cm_obs = (int*)(ws + plan.cm_obs.off);
+    h->cm_pt = (int*)(ws + plan.cm_pt.off);
+    h->cm_px = (double*)(ws + plan.cm_px.off);
+    h->cam_off = (int*)(ws + plan.cam_off.off);
+    h->chunks = (Chunk*)(ws + plan.chunks.off);
+    h->chunk_off = (int*)(ws + plan.chunk_off.off);
+    h->chunk_rows = (double*)(ws + plan.chunk_rows.off);
+    h->cold_list = (int*)(ws + plan.cold_list.off);
+    h->cold_off = (int*)(ws + plan.cold_off.off);
+    h->cold_rows = (double*)(ws + plan.cold_rows.off);
+    h->split_pts = (SplitPoint*)(ws + plan.split_pts.off);
+    h->split_rows = (double*)(ws + plan.split_rows.off);
+    h->hot_rows = (double*)(ws + plan.hot_rows.off);
+    h->Hcc = (double*)(ws + plan.Hcc.off);
+    h->Hpp = (double*)(ws + plan.Hpp.off);
+    h->Mc = ws + plan.Mc.off;
+    h->Mp = ws + plan.Mp.off;
+    void** vp[8] = {&h->vec.g, &h->vec.D, &h->vec.x, &h->vec.r, &h->vec.z, &h->vec.p, &h->vec.w, &h->vec.v};
+    for (int i = 0; i < 8; ++i) *vp[i] = ws + plan.vecs.off + i * plan.vec_bytes;
+    build_layout(h, cams, points, obs_cam, obs_pt, obs_px, ws, plan);
+    *out = h;
+  } catch (const Error& e) {
+    delete h;
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::exception& e) {
+    delete h;
+    set_last_error(e.what());
+    return CASPAR_EHIP;
+  }
+  set_last_error("");
+  return CASPAR_OK;
+}
+
+void caspar_ba_destroy(caspar_ba* h) { delete h; }
+
+int caspar_ba_get_params(caspar_ba* h, double* cams, double* points) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  if (cams && h->nc) {
+    k_cams_to_bal<<<blocks_for(h->nc, 256), 256, 0, h->stream>>>(h->nc, h->cam, h->cam_c2i, cams);
+    CBA_LAUNCHED();
+  }
+  if (points && h->np) {
+    k_points_out<<<blocks_for(h->np, 256), 256, 0, h->stream>>>(h->np, h->X, h->pt_c2i, points);
+    CBA_LAUNCHED();
+  }
+  sync(h);
+  CBA_API_END
+}
+
+int caspar_ba_set_params(caspar_ba* h, const double* cams, const double* points) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  if (cams) upload_cameras_bal(h, cams, h->cam);
+  if (points) upload_points(h, points, h->X);
+  h->linearized = false;
+  sync(h);
+  CBA_API_END
+}
+
+int caspar_ba_set_observations(caspar_ba* h, const double* obs_px) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(h->no == 0 || obs_px != nullptr, "obs_px is NULL");
+  if (h->no) {
+    k_set_px<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->obs_s2c, obs_px, h->px);
+    CBA_LAUNCHED();
+    k_set_cm_px<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->cm_obs, h->px, h->cm_px);
+    CBA_LAUNCHED();
+  }
+  h->linearized = false;
+  sync(h);
+  CBA_API_END
+}
+
+int caspar_project(int32_t n_cams, int32_t n_points, int64_t n_obs, const double* cams,
+                   const double* points, const int32_t* obs_cam, const int32_t* obs_pt,
+                   double* px_out, void* hip_stream) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(n_cams >= 0 && n_points >= 0 && n_obs >= 0, "negative size");
+  if (n_obs == 0) return CASPAR_OK;
+  CBA_REQUIRE(cams && points && obs_cam && obs_pt && px_out, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  k_project<<<blocks_for(n_obs, 256), 256, 0, st>>>(n_obs, cams, points, obs_cam, obs_pt, px_out);
+  CBA_LAUNCHED();
+  CBA_HIP(hipStreamSynchronize(st));
+  CBA_API_END
+}
+
+int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* cold_obs, int64_t* n_tiles,
+                          int32_t* matvec_groups) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  if (hot_cams) *hot_cams = h->K;
+  if (cold_obs) *cold_obs = h->n_cold;
+  if (n_tiles) *n_tiles = h->n_tiles;
+  if (matvec_groups) *matvec_groups = h->G;
+  CBA_API_END
+}
+
+}  // extern "C"

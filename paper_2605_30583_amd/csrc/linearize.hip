@@ -1,0 +1,423 @@
+// Linearisation of the Snavely problem (paper Section VI-A factor, Section V
+// tangent-space linearisation), the trial cost of the LM step and the
+// retraction theta (+) delta.
+//
+// Point-major pass (one wave per tile of <= 64 observations): residuals,
+// Jacobian blocks written once in a blocked structure-of-arrays (16-byte
+// chunks of two Jacobian columns x two rows for float64, four columns for
+// float32), the cost, and the point blocks g_p = J_p^T r, H_pp = J_p^T J_p
+// reduced with an in-wave segmented scan (points are contiguous inside a
+// tile).
+// Camera-major pass (one workgroup per chunk of <= 2048 observations of one
+// camera): recomputes r and J_c from the parameters and sums g_c = J_c^T r
+// and the upper triangle of H_cc = J_c^T J_c without atomics.
+#include "common.hpp"
+#include "model.hpp"
+
+namespace cba {
+
+__host__ __device__ constexpr int tri9(int k, int l) { return k * 9 - k * (k - 1) / 2 + (l - k); }
+
+__device__ inline double clamp_diag(double d) { return fmin(fmax(d, 1e-6), 1e32); }
+
+// ---------------------------------------------------------------------------
+// Point-major linearisation.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __restrict__ tiles,
+                                                    const uint32_t* __restrict__ meta,
+                                                    const double* __restrict__ px,
+                                                    const double* __restrict__ cam,
+                                                    const double* __restrict__ X, void* J, int no_pad,
+                                                    S* __restrict__ g, S* __restrict__ D,
+                                                    double* __restrict__ Hpp,
+                                                    double* __restrict__ split_rows, int nc,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  double cost = 0.0;
+  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += gridDim.x * 4) {
+    const Tile tl = tiles[t];
+    const int n = tile_nobs(tl.info);
+    const bool act = lane < n;
+    int lp = 100 + lane;
+    double v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = 0.0;
+    if (act) {
+      const int o = tl.obs_begin + lane;
+      const uint32_t m = meta[o];
+      const int ci = (int)(m & ((1u << kCamBits) - 1));
+      lp = (int)(m >> kCamBits);
+      const int pi = tl.pt_begin + lp;
+      const Cam<S> c = load_cam<S>(cam, ci);
+      const double* Xp = X + 3 * (size_t)pi;
+      const double2 q = reinterpret_cast<const double2*>(px)[o];
+      S r0, r1, col[12][2];
+      snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+      JStore<S>::store(J, no_pad, o, col);
+      cost = fma((double)r0, (double)r0, (double)r1 * (double)r1);
+      double jp[3][2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        jp[k][0] = col[9 + k][0];
+        jp[k][1] = col[9 + k][1];
+        v[k] = fma(jp[k][0], (double)r0, jp[k][1] * (double)r1);
+      }
+      v[3] = fma(jp[0][0], jp[0][0], jp[0][1] * jp[0][1]);
+      v[4] = fma(jp[0][0], jp[1][0], jp[0][1] * jp[1][1]);
+      v[5] = fma(jp[0][0], jp[2][0], jp[0][1] * jp[2][1]);
+      v[6] = fma(jp[1][0], jp[1][0], jp[1][1] * jp[1][1]);
+      v[7] = fma(jp[1][0], jp[2][0], jp[1][1] * jp[2][1]);
+      v[8] = fma(jp[2][0], jp[2][0], jp[2][1] * jp[2][1]);
+    }
+    // segmented suffix sums: the first lane of each point ends with its total
+    const int steps = tile_steps(tl.info);
+    for (int s = 0, d = 1; s < steps; ++s, d <<= 1) {
+      const int olp = __shfl_down(lp, d, kWave);
+      const bool take = (lane + d < kWave) && olp == lp;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double o = __shfl_down(v[k], d, kWave);
+        if (take) v[k] += o;
+      }
+    }
+    const int prev = __shfl_up(lp, 1, kWave);
+    const bool head = act && (lane == 0 || prev != lp);
+    if (head) {
+      if (tile_split(tl.info)) {
+        double* row = split_rows + (size_t)tl.split_row * kPtRowWidth;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) row[k] = v[k];
+      } else {
+        const int pi = tl.pt_begin + lp;
+        const size_t b = 9 * (size_t)nc + 3 * (size_t)pi;
+        g[b] = (S)v[0];
+        g[b + 1] = (S)v[1];
+        g[b + 2] = (S)v[2];
+        double* H = Hpp + 6 * (size_t)pi;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) H[k] = v[3 + k];
+        D[b] = (S)clamp_diag(v[3]);
+        D[b + 1] = (S)clamp_diag(v[6]);
+        D[b + 2] = (S)clamp_diag(v[8]);
+      }
+    }
+  }
+  const double tot = block_sum(cost, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
+}
+
+// Points with more than 64 observations: sum their tiles' rows.
+template <typename S>
+__global__ void k_lin_split(int n_split, const SplitPoint* __restrict__ sp,
+                            const double* __restrict__ split_rows, S* g, S* D, double* Hpp, int nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_split) return;
+  const SplitPoint s = sp[i];
+  double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r = 0; r < s.nrows; ++r)
+    for (int k = 0; k < 9; ++k) v[k] += split_rows[(size_t)(s.row_begin + r) * kPtRowWidth + k];
+  const size_t b = 9 * (size_t)nc + 3 * (size_t)s.pt;
+  for (int k = 0; k < 3; ++k) g[b + k] = (S)v[k];
+  for (int k = 0; k < 6; ++k) Hpp[6 * (size_t)s.pt + k] = v[3 + k];
+  D[b] = (S)clamp_diag(v[3]);
+  D[b + 1] = (S)clamp_diag(v[6]);
+  D[b + 2] = (S)clamp_diag(v[8]);
+}
+
+// Points without observations: g = 0, H = 0, D at its floor.
+template <typename S>
+__global__ void k_lin_orphans(int n_orphan, S* g, S* D, double* Hpp, int nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_orphan) return;
+  const size_t b = 9 * (size_t)nc + 3 * (size_t)i;
+  for (int k = 0; k < 3; ++k) {
+    g[b + k] = (S)0;
+    D[b + k] = (S)1e-6;
+  }
+  for (int k = 0; k < 6; ++k) Hpp[6 * (size_t)i + k] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Camera-major block sums: one workgroup per chunk.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chunks,
+                                                  const int* __restrict__ cm_pt,
+                                                  const double* __restrict__ cm_px,
+                                                  const double* __restrict__ cam,
+                                                  const double* __restrict__ X,
+                                                  double* __restrict__ rows) {
+  __shared__ double lds[4][kCamRowWidth];
+  const Chunk ch = chunks[blockIdx.x];
+  const Cam<S> c = load_cam<S>(cam, ch.cam);
+  double acc[kCamRowWidth];
+#pragma unroll
+  for (int k = 0; k < kCamRowWidth; ++k) acc[k] = 0.0;
+  for (int j = ch.begin + threadIdx.x; j < ch.end; j += blockDim.x) {
+    const int pi = cm_pt[j];
+    const double* Xp = X + 3 * (size_t)pi;
+    const double2 q = reinterpret_cast<const double2*>(cm_px)[j];
+    S r0, r1, col[12][2];
+    snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+    double jc[9][2];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      jc[k][0] = col[k][0];
+      jc[k][1] = col[k][1];
+      acc[k] = fma(jc[k][0], (double)r0, fma(jc[k][1], (double)r1, acc[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int l = k; l < 9; ++l)
+        acc[9 + tri9(k, l)] = fma(jc[k][0], jc[l][0], fma(jc[k][1], jc[l][1], acc[9 + tri9(k, l)]));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kCamRowWidth; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) lds[wv][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kCamRowWidth) {
+    const double s = lds[0][threadIdx.x] + lds[1][threadIdx.x] + lds[2][threadIdx.x] + lds[3][threadIdx.x];
+    rows[(size_t)blockIdx.x * kCamRowWidth + threadIdx.x] = s;
+  }
+}
+
+// Per camera: sum the chunk rows into g_c, H_cc and D_c.
+template <typename S>
+__global__ void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
+                                const double* __restrict__ rows, S* g, S* D, double* Hcc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nc * kCamRowWidth) return;
+  const int c = (int)(i / kCamRowWidth), k = (int)(i % kCamRowWidth);
+  double s = 0.0;
+  for (int q = chunk_off[c]; q < chunk_off[c + 1]; ++q) s += rows[(size_t)q * kCamRowWidth + k];
+  if (k < 9) {
+    g[9 * (size_t)c + k] = (S)s;
+  } else {
+    const int h = k - 9;
+    Hcc[45 * (size_t)c + h] = s;
+    for (int d = 0; d < 9; ++d)
+      if (tri9(d, d) == h) D[9 * (size_t)c + d] = (S)clamp_diag(s);
+  }
+}
+
+// Sum of column `col` of the first n partial slots into scal->red[slot].
+__global__ void k_sum_partials(int n, const double* __restrict__ partials, int col, DevScalars* sc,
+                               int slot) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[(size_t)i * kPartialWidth + col];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) sc->red[slot] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Cost only (trial step, float64 re-evaluation).
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restrict__ tiles,
+                                              const uint32_t* __restrict__ meta,
+                                              const double* __restrict__ px,
+                                              const double* __restrict__ cam,
+                                              const double* __restrict__ X,
+                                              double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  double cost = 0.0;
+  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += gridDim.x * 4) {
+    const Tile tl = tiles[t];
+    if (lane < tile_nobs(tl.info)) {
+      const int o = tl.obs_begin + lane;
+      const uint32_t m = meta[o];
+      const int ci = (int)(m & ((1u << kCamBits) - 1));
+      const int pi = tl.pt_begin + (int)(m >> kCamBits);
+      const Cam<S> c = load_cam<S>(cam, ci);
+      const double* Xp = X + 3 * (size_t)pi;
+      const double2 q = reinterpret_cast<const double2*>(px)[o];
+      S r0, r1;
+      snavely_residual<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1);
+      cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
+    }
+  }
+  const double tot = block_sum(cost, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Retraction: R Exp(dw), t + dt, calibration + d, X + dX (Section V).
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_retract_cams(int nc, const double* __restrict__ cam, const S* __restrict__ delta,
+                               double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double* in = cam + (size_t)c * kCamStride;
+  const S* d = delta + 9 * (size_t)c;
+  double E[9], R[9];
+  so3_exp((double)d[0], (double)d[1], (double)d[2], E);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      R[3 * i + j] = in[3 * i] * E[j] + in[3 * i + 1] * E[3 + j] + in[3 * i + 2] * E[6 + j];
+  double* o = out + (size_t)c * kCamStride;
+  for (int i = 0; i < 9; ++i) o[i] = R[i];
+  for (int i = 0; i < 6; ++i) o[9 + i] = in[9 + i] + (double)d[3 + i];
+  o[15] = 0.0;
+}
+
+template <typename S>
+__global__ void k_retract_points(int np, const double* __restrict__ X, const S* __restrict__ delta,
+                                 double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < 3 * (int64_t)np) out[i] = X[i] + (double)delta[i];
+}
+
+// ---------------------------------------------------------------------------
+// Parity hook: residuals and Jacobian blocks in caller order, float64.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
+                             const double* __restrict__ px, const double* __restrict__ cam,
+                             const double* __restrict__ X, const void* J, int no_pad,
+                             const int* __restrict__ s2c, double* resid, double* jc, double* jp) {
+  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (t >= n_tiles) return;
+  const Tile tl = tiles[t];
+  if (lane >= tile_nobs(tl.info)) return;
+  const int o = tl.obs_begin + lane;
+  const uint32_t m = meta[o];
+  const int ci = (int)(m & ((1u << kCamBits) - 1));
+  const int pi = tl.pt_begin + (int)(m >> kCamBits);
+  const size_t c = (size_t)s2c[o];
+  if (resid) {
+    const Cam<S> cm = load_cam<S>(cam, ci);
+    const double* Xp = X + 3 * (size_t)pi;
+    const double2 q = reinterpret_cast<const double2*>(px)[o];
+    S r0, r1;
+    snavely_residual<S>(cm, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1);
+    resid[2 * c] = r0;
+    resid[2 * c + 1] = r1;
+  }
+  S col[12][2];
+  JStore<S>::load(J, no_pad, o, col);
+  if (jc)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 9; ++j) jc[18 * c + 9 * i + j] = col[j][i];
+  if (jp)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j) jp[6 * c + 3 * i + j] = col[9 + j][i];
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers.
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int threads) {
+  return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+static unsigned tile_grid(int n_tiles) {
+  return (unsigned)std::max(1, std::min((n_tiles + 3) / 4, 2048));
+}
+
+template <typename S>
+static void linearize_t(caspar_ba* h) {
+  hipStream_t st = h->stream;
+  S* g = (S*)h->vec.g;
+  S* D = (S*)h->vec.D;
+  const unsigned tg = tile_grid(h->n_tiles);
+  if (h->n_tiles > 0) {
+    k_lin_points<S><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J,
+                                         h->no_pad, g, D, h->Hpp, h->split_rows, h->nc, h->partials);
+    CBA_LAUNCHED();
+    k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
+    CBA_LAUNCHED();
+  } else {
+    CBA_HIP(hipMemsetAsync(h->scal->red, 0, sizeof(double), st));
+  }
+  if (h->n_split_pts > 0) {
+    k_lin_split<S><<<nblk(h->n_split_pts, 256), 256, 0, st>>>(h->n_split_pts, h->split_pts, h->split_rows,
+                                                              g, D, h->Hpp, h->nc);
+    CBA_LAUNCHED();
+  }
+  if (h->n_orphan_pts > 0) {
+    k_lin_orphans<S><<<nblk(h->n_orphan_pts, 256), 256, 0, st>>>(h->n_orphan_pts, g, D, h->Hpp, h->nc);
+    CBA_LAUNCHED();
+  }
+  if (h->n_chunks > 0) {
+    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, h->X, h->chunk_rows);
+    CBA_LAUNCHED();
+  }
+  if (h->nc > 0) {
+    k_lin_cam_final<S><<<nblk((int64_t)h->nc * kCamRowWidth, 256), 256, 0, st>>>(h->nc, h->chunk_off,
+                                                                             h->chunk_rows, g, D, h->Hcc);
+    CBA_LAUNCHED();
+  }
+}
+
+void run_linearize(caspar_ba* h) {
+  if (h->prec == CASPAR_FP64)
+    linearize_t<double>(h);
+  else
+    linearize_t<float>(h);
+  const DevScalars s = read_scalars(h);
+  h->cost = 0.5 * s.red[0];
+  h->gmax = run_absmax(h, h->vec.g);
+  h->linearized = true;
+  h->bj_lambda = -1.0;
+}
+
+double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
+  if (h->n_tiles == 0) return 0.0;
+  hipStream_t st = h->stream;
+  const unsigned tg = tile_grid(h->n_tiles);
+  if (fp64 || h->prec == CASPAR_FP64)
+    k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials);
+  else
+    k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials);
+  CBA_LAUNCHED();
+  k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 1);
+  CBA_LAUNCHED();
+  return 0.5 * read_scalars(h).red[1];
+}
+
+template <typename S>
+static void retract_t(caspar_ba* h, const S* delta) {
+  hipStream_t st = h->stream;
+  if (h->nc) {
+    k_retract_cams<S><<<nblk(h->nc, 256), 256, 0, st>>>(h->nc, h->cam, delta, h->cam_trial);
+    CBA_LAUNCHED();
+  }
+  if (h->np) {
+    k_retract_points<S><<<nblk(3 * (int64_t)h->np, 256), 256, 0, st>>>(h->np, h->X, delta + 9 * (size_t)h->nc,
+                                                                       h->X_trial);
+    CBA_LAUNCHED();
+  }
+}
+
+void run_retract(caspar_ba* h, const void* delta) {
+  if (h->prec == CASPAR_FP64)
+    retract_t<double>(h, (const double*)delta);
+  else
+    retract_t<float>(h, (const float*)delta);
+}
+
+void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* jp) {
+  if (h->n_tiles == 0) return;
+  const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
+  if (h->prec == CASPAR_FP64)
+    k_export_lin<double><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
+                                                      h->J, h->no_pad, h->obs_s2c, resid, jc, jp);
+  else
+    k_export_lin<float><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
+                                                     h->J, h->no_pad, h->obs_s2c, resid, jc, jp);
+  CBA_LAUNCHED();
+}
+
+}  // namespace cba

@@ -1,0 +1,275 @@
+// Device-side camera model: the Snavely reprojection factor of the paper's
+// Section VI-A and its tangent-space Jacobian (Section V), plus the SO(3)
+// exponential, logarithm and inverse right Jacobian used at the boundary.
+#pragma once
+
+#include "common.hpp"
+
+namespace cba {
+
+// Camera in registers, converted to the working precision T.
+template <typename T>
+struct Cam {
+  T R[9];  // row-major
+  T t[3];
+  T f, k1, k2;
+};
+
+// Loads one 16-double camera row [R(9) t(3) f k1 k2 pad] (128-byte aligned).
+template <typename T>
+__device__ inline Cam<T> load_cam(const double* __restrict__ camtab, int c) {
+  const double2* row = reinterpret_cast<const double2*>(camtab + (size_t)c * kCamStride);
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double2 q = row[i];
+    v[2 * i] = q.x;
+    v[2 * i + 1] = q.y;
+  }
+  Cam<T> cam;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cam.R[i] = (T)v[i];
+  cam.t[0] = (T)v[9];
+  cam.t[1] = (T)v[10];
+  cam.t[2] = (T)v[11];
+  cam.f = (T)v[12];
+  cam.k1 = (T)v[13];
+  cam.k2 = (T)v[14];
+  return cam;
+}
+
+// Residual of one observation.  P = R X + t; the depth keeps its sign away
+// from zero (d + eps sign(d), sign(0) = +1); p = -P_xy / d;
+// radial = 1 + k1 |p|^2 + k2 |p|^4; r = f radial p - px.
+template <typename T>
+__device__ inline void snavely_residual(const Cam<T>& c, T X0, T X1, T X2, T px0, T px1, T& r0,
+                                        T& r1) {
+  const T P0 = fma(c.R[0], X0, fma(c.R[1], X1, fma(c.R[2], X2, c.t[0])));
+  const T P1 = fma(c.R[3], X0, fma(c.R[4], X1, fma(c.R[5], X2, c.t[1])));
+  const T P2 = fma(c.R[6], X0, fma(c.R[7], X1, fma(c.R[8], X2, c.t[2])));
+  const T d = P2 + (P2 >= (T)0 ? Scalar<T>::eps() : -Scalar<T>::eps());
+  const T id = (T)1 / d;
+  const T p0 = -P0 * id, p1 = -P1 * id;
+  const T n2 = fma(p0, p0, p1 * p1);
+  const T rad = fma(n2, fma(c.k2, n2, c.k1), (T)1);
+  const T fr = c.f * rad;
+  r0 = fma(fr, p0, -px0);
+  r1 = fma(fr, p1, -px1);
+}
+
+// Residual and Jacobian columns.  col[j] = (J[0][j], J[1][j]) for the 12
+// columns [dw(3), dt(3), df, dk1, dk2, dX(3)].
+//   du/dp = f (radial I + 2 (k1 + 2 k2 |p|^2) p p^T) =: A
+//   dp/dP = -(1/d) [I | p]          => B = du/dP = -(1/d) [A | A p]
+//   dP/dt = I, dP/dX = R, dP/dw = -R [X]x (right perturbation)
+//   J_t = B, J_X = B R, row i of J_w = X x (row i of J_X)
+//   J_f = radial p, J_k1 = f |p|^2 p, J_k2 = f |p|^4 p.
+template <typename T>
+__device__ inline void snavely_jacobian(const Cam<T>& c, T X0, T X1, T X2, T px0, T px1, T& r0,
+                                        T& r1, T col[12][2]) {
+  const T P0 = fma(c.R[0], X0, fma(c.R[1], X1, fma(c.R[2], X2, c.t[0])));
+  const T P1 = fma(c.R[3], X0, fma(c.R[4], X1, fma(c.R[5], X2, c.t[1])));
+  const T P2 = fma(c.R[6], X0, fma(c.R[7], X1, fma(c.R[8], X2, c.t[2])));
+  const T d = P2 + (P2 >= (T)0 ? Scalar<T>::eps() : -Scalar<T>::eps());
+  const T id = (T)1 / d;
+  const T p0 = -P0 * id, p1 = -P1 * id;
+  const T n2 = fma(p0, p0, p1 * p1);
+  const T rad = fma(n2, fma(c.k2, n2, c.k1), (T)1);
+  const T fr = c.f * rad;
+  r0 = fma(fr, p0, -px0);
+  r1 = fma(fr, p1, -px1);
+
+  const T fs = c.f * (T)2 * fma((T)2 * c.k2, n2, c.k1);
+  const T a00 = fma(fs * p0, p0, fr);
+  const T a01 = fs * p0 * p1;
+  const T a11 = fma(fs * p1, p1, fr);
+  const T m = -id;
+  const T B00 = m * a00, B01 = m * a01, B10 = m * a01, B11 = m * a11;
+  const T B02 = fma(B00, p0, B01 * p1);
+  const T B12 = fma(B10, p0, B11 * p1);
+  // J_X = B R
+  T Jx0[3], Jx1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Jx0[k] = fma(B00, c.R[k], fma(B01, c.R[3 + k], B02 * c.R[6 + k]));
+    Jx1[k] = fma(B10, c.R[k], fma(B11, c.R[3 + k], B12 * c.R[6 + k]));
+  }
+  // J_w rows: X x J_X rows
+  col[0][0] = fma(X1, Jx0[2], -X2 * Jx0[1]);
+  col[1][0] = fma(X2, Jx0[0], -X0 * Jx0[2]);
+  col[2][0] = fma(X0, Jx0[1], -X1 * Jx0[0]);
+  col[0][1] = fma(X1, Jx1[2], -X2 * Jx1[1]);
+  col[1][1] = fma(X2, Jx1[0], -X0 * Jx1[2]);
+  col[2][1] = fma(X0, Jx1[1], -X1 * Jx1[0]);
+  col[3][0] = B00;
+  col[3][1] = B10;
+  col[4][0] = B01;
+  col[4][1] = B11;
+  col[5][0] = B02;
+  col[5][1] = B12;
+  col[6][0] = rad * p0;
+  col[6][1] = rad * p1;
+  const T fn2 = c.f * n2;
+  col[7][0] = fn2 * p0;
+  col[7][1] = fn2 * p1;
+  col[8][0] = fn2 * n2 * p0;
+  col[8][1] = fn2 * n2 * p1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    col[9 + k][0] = Jx0[k];
+    col[9 + k][1] = Jx1[k];
+  }
+}
+
+// Exp of an angle-axis vector (Rodrigues), row-major 3x3.
+// R = I + s [w]x + c [w]x^2 with s = sin(a)/a, c = (1 - cos a)/a^2;
+// series below a = 1e-4.
+__device__ inline void so3_exp(double w0, double w1, double w2, double R[9]) {
+  const double a2 = w0 * w0 + w1 * w1 + w2 * w2;
+  double s, c;
+  if (a2 < 1e-8) {
+    s = 1.0 - a2 / 6.0 + a2 * a2 / 120.0;
+    c = 0.5 - a2 / 24.0 + a2 * a2 / 720.0;
+  } else {
+    const double a = sqrt(a2);
+    double sn, cs;
+    sincos(a, &sn, &cs);
+    s = sn / a;
+    c = (1.0 - cs) / a2;
+  }
+  // [w]x^2 = w w^T - a2 I
+  R[0] = 1.0 + c * (w0 * w0 - a2);
+  R[1] = c * w0 * w1 - s * w2;
+  R[2] = c * w0 * w2 + s * w1;
+  R[3] = c * w1 * w0 + s * w2;
+  R[4] = 1.0 + c * (w1 * w1 - a2);
+  R[5] = c * w1 * w2 - s * w0;
+  R[6] = c * w2 * w0 - s * w1;
+  R[7] = c * w2 * w1 + s * w0;
+  R[8] = 1.0 + c * (w2 * w2 - a2);
+}
+
+// Log of a rotation matrix as an angle-axis vector, through the unit
+// quaternion (largest-component branch, accurate up to angle pi).
+__device__ inline void so3_log(const double R[9], double w[3]) {
+  const double tr = R[0] + R[4] + R[8];
+  double q0, q1, q2, q3;  // w, x, y, z
+  if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+    q0 = 0.5 * sqrt(fmax(0.0, 1.0 + tr));
+    const double s = 0.25 / q0;
+    q1 = (R[7] - R[5]) * s;
+    q2 = (R[2] - R[6]) * s;
+    q3 = (R[3] - R[1]) * s;
+  } else if (R[0] >= R[4] && R[0] >= R[8]) {
+    q1 = 0.5 * sqrt(fmax(0.0, 1.0 + R[0] - R[4] - R[8]));
+    const double s = 0.25 / q1;
+    q2 = (R[1] + R[3]) * s;
+    q3 = (R[2] + R[6]) * s;
+    q0 = (R[7] - R[5]) * s;
+  } else if (R[4] >= R[8]) {
+    q2 = 0.5 * sqrt(fmax(0.0, 1.0 + R[4] - R[0] - R[8]));
+    const double s = 0.25 / q2;
+    q1 = (R[1] + R[3]) * s;
+    q3 = (R[5] + R[7]) * s;
+    q0 = (R[2] - R[6]) * s;
+  } else {
+    q3 = 0.5 * sqrt(fmax(0.0, 1.0 + R[8] - R[0] - R[4]));
+    const double s = 0.25 / q3;
+    q1 = (R[2] + R[6]) * s;
+    q2 = (R[5] + R[7]) * s;
+    q0 = (R[3] - R[1]) * s;
+  }
+  if (q0 < 0.0) {
+    q0 = -q0;
+    q1 = -q1;
+    q2 = -q2;
+    q3 = -q3;
+  }
+  const double vn = sqrt(q1 * q1 + q2 * q2 + q3 * q3);
+  double k;
+  if (vn < 1e-12) {
+    k = 2.0 / q0;  // angle ~ 2 vn / q0
+  } else {
+    k = 2.0 * atan2(vn, q0) / vn;
+  }
+  w[0] = k * q1;
+  w[1] = k * q2;
+  w[2] = k * q3;
+}
+
+// g_tangent = J_r^-1(w)^T g_aa, the gradient with respect to a right
+// perturbation from the gradient with respect to the angle-axis vector.
+// J_r^-1(w) = I + 1/2 [w]x + (1/a^2 - cot(a/2) / (2a)) [w]x^2.
+__device__ inline void so3_grad_to_tangent(const double w[3], const double g[3], double out[3]) {
+  const double a2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  double c;
+  if (a2 < 1e-6) {
+    c = 1.0 / 12.0 + a2 / 720.0;
+  } else {
+    const double a = sqrt(a2);
+    c = 1.0 / a2 - 1.0 / (2.0 * a * tan(0.5 * a));
+  }
+  // J^T g = g - 1/2 [w]x g + c [w]x^2 g   ([w]x^T = -[w]x, ([w]x^2)^T = [w]x^2)
+  const double wxg0 = w[1] * g[2] - w[2] * g[1];
+  const double wxg1 = w[2] * g[0] - w[0] * g[2];
+  const double wxg2 = w[0] * g[1] - w[1] * g[0];
+  const double wg = w[0] * g[0] + w[1] * g[1] + w[2] * g[2];
+  // [w]x^2 g = w (w.g) - a2 g
+  out[0] = g[0] - 0.5 * wxg0 + c * (w[0] * wg - a2 * g[0]);
+  out[1] = g[1] - 0.5 * wxg1 + c * (w[1] * wg - a2 * g[1]);
+  out[2] = g[2] - 0.5 * wxg2 + c * (w[2] * wg - a2 * g[2]);
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// Jacobian storage: blocked structure-of-arrays of 16-byte chunks, chunk-major
+// ([chunk][observation]), so a wave's 64 lanes read 1 KiB contiguous per
+// chunk.
+template <typename S>
+struct JStore;
+
+// float64: 12 chunks, chunk j = column j (two rows).
+template <>
+struct JStore<double> {
+  static constexpr int kChunks = 12;
+  __device__ static void store(void* J, int no_pad, int o, const double col[12][2]) {
+    double2* Jv = reinterpret_cast<double2*>(J);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) Jv[(size_t)j * no_pad + o] = make_double2(col[j][0], col[j][1]);
+  }
+  __device__ static void load(const void* J, int no_pad, int o, double col[12][2]) {
+    const dvec2* Jv = reinterpret_cast<const dvec2*>(J);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      const dvec2 v = __builtin_nontemporal_load(&Jv[(size_t)j * no_pad + o]);
+      col[j][0] = v.x;
+      col[j][1] = v.y;
+    }
+  }
+};
+
+// float32: 6 chunks, chunk k = columns 2k, 2k+1 (two rows each).
+template <>
+struct JStore<float> {
+  static constexpr int kChunks = 6;
+  __device__ static void store(void* J, int no_pad, int o, const float col[12][2]) {
+    float4* Jv = reinterpret_cast<float4*>(J);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      Jv[(size_t)k * no_pad + o] = make_float4(col[2 * k][0], col[2 * k][1], col[2 * k + 1][0], col[2 * k + 1][1]);
+  }
+  __device__ static void load(const void* J, int no_pad, int o, float col[12][2]) {
+    const fvec4* Jv = reinterpret_cast<const fvec4*>(J);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const fvec4 v = __builtin_nontemporal_load(&Jv[(size_t)k * no_pad + o]);
+      col[2 * k][0] = v.x;
+      col[2 * k][1] = v.y;
+      col[2 * k + 1][0] = v.z;
+      col[2 * k + 1][1] = v.w;
+    }
+  }
+};
+
+}  // namespace cba

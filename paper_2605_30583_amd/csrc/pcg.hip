@@ -1,0 +1,489 @@
+// Block-Jacobi preconditioned conjugate gradients on the damped normal
+// equations (PCGNR, Section V and the paper's glossary): one preconditioner
+// block per camera (9x9) and per point (3x3), the diagonal blocks of
+// J^T J + lambda D, inverted by Cholesky in float64.
+//
+// All PCG scalars (rho, alpha, beta, |r|^2, the stop flag) stay on the
+// device: every kernel reads them and returns at once when the solve is
+// done, so the host enqueues several iterations between polls.  Dot
+// products are accumulated in float64 per workgroup and summed in a fixed
+// order by a single-workgroup kernel (deterministic).
+#include <cmath>
+
+#include "common.hpp"
+#include "model.hpp"
+
+namespace cba {
+
+__host__ __device__ constexpr int tri_idx(int n, int k, int l) {
+  return k * n - k * (k - 1) / 2 + (l - k);
+}
+
+// Inverse of the n x n symmetric positive definite matrix given by its packed
+// upper triangle plus lambda * diag(d); result packed the same way.
+// Cholesky A = L L^T, W = L^-1, A^-1 = W^T W.  On a non-positive pivot the
+// diagonal is raised by 1e-12 trace(A) and the factorisation retried once;
+// if that fails too the inverse of the diagonal is returned.
+template <int n>
+__device__ void spd_inverse(const double* __restrict__ Hup, const double* dg, double lambda,
+                            double* __restrict__ out) {
+  double A[n][n], L[n][n], W[n][n];
+  double tr = 0.0;
+#pragma unroll
+  for (int k = 0; k < n; ++k)
+#pragma unroll
+    for (int l = k; l < n; ++l) {
+      const double v = Hup[tri_idx(n, k, l)] + (k == l ? lambda * dg[k] : 0.0);
+      A[k][l] = v;
+      A[l][k] = v;
+      if (k == l) tr += v;
+    }
+  bool ok = false;
+  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+    const double jitter = attempt == 0 ? 0.0 : 1e-12 * fabs(tr);
+    ok = true;
+    for (int j = 0; j < n && ok; ++j) {
+      double s = A[j][j] + jitter;
+      for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+      if (!(s > 0.0) || !isfinite(s)) {
+        ok = false;
+        break;
+      }
+      L[j][j] = sqrt(s);
+      for (int i = j + 1; i < n; ++i) {
+        double t = A[i][j];
+        for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+        L[i][j] = t / L[j][j];
+      }
+    }
+  }
+  if (!ok) {
+#pragma unroll
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int l = k; l < n; ++l) out[tri_idx(n, k, l)] = (k == l && A[k][k] > 0.0) ? 1.0 / A[k][k] : 0.0;
+    return;
+  }
+  for (int j = 0; j < n; ++j) {
+    W[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[i][k] * W[k][j];
+      W[i][j] = -s / L[i][i];
+    }
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = a; b < n; ++b) {
+      double s = 0.0;
+      for (int m = b; m < n; ++m) s += W[m][a] * W[m][b];
+      out[tri_idx(n, a, b)] = s;
+    }
+}
+
+template <typename S>
+__global__ void k_bj_cams(int nc, const double* __restrict__ Hcc, const S* __restrict__ D, double lambda,
+                          S* __restrict__ Mc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double dg[9], inv[45];
+  for (int k = 0; k < 9; ++k) dg[k] = (double)D[9 * (size_t)c + k];
+  spd_inverse<9>(Hcc + 45 * (size_t)c, dg, lambda, inv);
+  for (int k = 0; k < 45; ++k) Mc[45 * (size_t)c + k] = (S)inv[k];
+}
+
+template <typename S>
+__global__ void k_bj_points(int np, const double* __restrict__ Hpp, const S* __restrict__ Dp, double lambda,
+                            S* __restrict__ Mp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  double dg[3], inv[6];
+  for (int k = 0; k < 3; ++k) dg[k] = (double)Dp[3 * (size_t)i + k];
+  spd_inverse<3>(Hpp + 6 * (size_t)i, dg, lambda, inv);
+  for (int k = 0; k < 6; ++k) Mp[6 * (size_t)i + k] = (S)inv[k];
+}
+
+// z = M^-1 r for block b (camera if b < nc, else point b - nc).
+template <typename S, int n>
+__device__ inline void block_apply(const S* __restrict__ Minv, const S* __restrict__ r, S* __restrict__ z,
+                                   double& rz, double& rr) {
+  S rv[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) rv[k] = r[k];
+  S mv[n * (n + 1) / 2];
+#pragma unroll
+  for (int k = 0; k < n * (n + 1) / 2; ++k) mv[k] = Minv[k];
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    S s = (S)0;
+#pragma unroll
+    for (int l = 0; l < n; ++l) s = fma(mv[k <= l ? tri_idx(n, k, l) : tri_idx(n, l, k)], rv[l], s);
+    z[k] = s;
+    rz = fma((double)rv[k], (double)s, rz);
+    rr = fma((double)rv[k], (double)rv[k], rr);
+  }
+}
+
+template <typename S>
+__global__ void k_bj_apply(int nc, int np, const S* __restrict__ Mc, const S* __restrict__ Mp,
+                           const S* __restrict__ r, S* __restrict__ z) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if (b < nc) {
+    block_apply<S, 9>(Mc + 45 * b, r + 9 * b, z + 9 * b, rz, rr);
+  } else if (b < (int64_t)nc + np) {
+    const int64_t i = b - nc;
+    const size_t o = 9 * (size_t)nc + 3 * (size_t)i;
+    block_apply<S, 3>(Mp + 6 * i, r + o, z + o, rz, rr);
+  }
+}
+
+// x = 0, r = +-b, z = M^-1 r, p = z; partials: r^T z, r^T r.
+template <typename S>
+__global__ __launch_bounds__(256) void k_pcg_init(int nc, int np, const S* __restrict__ Mc,
+                                                  const S* __restrict__ Mp, const S* __restrict__ b,
+                                                  double sign, S* __restrict__ x, S* __restrict__ r,
+                                                  S* __restrict__ z, S* __restrict__ p,
+                                                  double* __restrict__ partials) {
+  __shared__ double red[4];
+  double rz = 0.0, rr = 0.0;
+  const int64_t nb = (int64_t)nc + np;
+  for (int64_t blk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; blk < nb;
+       blk += (int64_t)gridDim.x * blockDim.x) {
+    const bool cam = blk < nc;
+    const int n = cam ? 9 : 3;
+    const size_t o = cam ? 9 * (size_t)blk : 9 * (size_t)nc + 3 * (size_t)(blk - nc);
+    for (int k = 0; k < n; ++k) {
+      r[o + k] = (S)(sign * (double)b[o + k]);
+      x[o + k] = (S)0;
+    }
+    if (cam)
+      block_apply<S, 9>(Mc + 45 * blk, r + o, z + o, rz, rr);
+    else
+      block_apply<S, 3>(Mp + 6 * (blk - nc), r + o, z + o, rz, rr);
+    for (int k = 0; k < n; ++k) p[o + k] = z[o + k];
+  }
+  const double a = block_sum(rz, red);
+  const double c = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * kPartialWidth] = a;
+    partials[(size_t)blockIdx.x * kPartialWidth + 1] = c;
+  }
+}
+
+__global__ void k_pcg_scalar0(int n, const double* __restrict__ partials, double tol, int max_iter,
+                              DevScalars* sc) {
+  __shared__ double red[16];
+  double a = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += partials[(size_t)i * kPartialWidth];
+    c += partials[(size_t)i * kPartialWidth + 1];
+  }
+  a = block_sum(a, red);
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    sc->rho = a;
+    sc->bb = c;
+    sc->rr = c;
+    sc->tol2 = tol * tol * c;
+    sc->iter = 0;
+    sc->max_iter = max_iter;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+    sc->done = 0;
+    sc->reason = PCG_RUNNING;
+    if (c == 0.0) {
+      sc->done = 1;
+      sc->reason = PCG_ZERO_RHS;
+    } else if (!isfinite(a) || !isfinite(c) || max_iter <= 0) {
+      sc->done = 1;
+      sc->reason = max_iter <= 0 ? PCG_MAXITER : PCG_BREAKDOWN;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha w; z = M^-1 r; partials: r^T r, r^T z.
+template <typename S>
+__global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __restrict__ Mc,
+                                                    const S* __restrict__ Mp, S* __restrict__ x,
+                                                    S* __restrict__ r, S* __restrict__ z,
+                                                    const S* __restrict__ p, const S* __restrict__ w,
+                                                    const DevScalars* __restrict__ sc,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[4];
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  double rz = 0.0, rr = 0.0;
+  const int64_t nb = (int64_t)nc + np;
+  for (int64_t blk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; blk < nb;
+       blk += (int64_t)gridDim.x * blockDim.x) {
+    const bool cam = blk < nc;
+    const int n = cam ? 9 : 3;
+    const size_t o = cam ? 9 * (size_t)blk : 9 * (size_t)nc + 3 * (size_t)(blk - nc);
+    for (int k = 0; k < n; ++k) {
+      x[o + k] = (S)fma(alpha, (double)p[o + k], (double)x[o + k]);
+      r[o + k] = (S)fma(-alpha, (double)w[o + k], (double)r[o + k]);
+    }
+    if (cam)
+      block_apply<S, 9>(Mc + 45 * blk, r + o, z + o, rz, rr);
+    else
+      block_apply<S, 3>(Mp + 6 * (blk - nc), r + o, z + o, rz, rr);
+  }
+  const double a = block_sum(rr, red);
+  const double c = block_sum(rz, red);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * kPartialWidth] = a;
+    partials[(size_t)blockIdx.x * kPartialWidth + 1] = c;
+  }
+}
+
+__global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevScalars* sc) {
+  __shared__ double red[16];
+  if (sc->done) return;
+  double a = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += partials[(size_t)i * kPartialWidth];
+    c += partials[(size_t)i * kPartialWidth + 1];
+  }
+  a = block_sum(a, red);
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    sc->rr = a;
+    if (!isfinite(a) || !isfinite(c)) {
+      sc->done = 1;
+      sc->reason = PCG_BREAKDOWN;
+    } else if (a <= sc->tol2) {
+      sc->done = 1;
+      sc->reason = PCG_CONVERGED;
+    } else {
+      sc->beta = c / sc->rho;
+      sc->rho = c;
+      if (sc->iter >= sc->max_iter) {
+        sc->done = 1;
+        sc->reason = PCG_MAXITER;
+      }
+    }
+  }
+}
+
+// p = z + beta p.
+template <typename S>
+__global__ __launch_bounds__(256) void k_pcg_p(int64_t N, const S* __restrict__ z, S* __restrict__ p,
+                                               const DevScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const double beta = sc->beta;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (S)fma(beta, (double)p[i], (double)z[i]);
+}
+
+// Partials of sum a b and (if e) sum a e b.
+template <typename S>
+__global__ __launch_bounds__(256) void k_dot(int64_t N, const S* __restrict__ a, const S* __restrict__ b,
+                                             const S* __restrict__ e, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double t = (double)a[i] * (double)b[i];
+    s = e ? fma(t, (double)e[i], s) : s + t;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = s;
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_absmax(int64_t N, const S* __restrict__ a, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    s = fmax(s, fabs((double)a[i]));
+  s = block_max(s, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = s;
+}
+
+__global__ void k_reduce_partials(int n, const double* __restrict__ partials, int is_max, DevScalars* sc,
+                                  int slot) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = partials[(size_t)i * kPartialWidth];
+    s = is_max ? fmax(s, v) : s + v;
+  }
+  s = is_max ? block_max(s, red) : block_sum(s, red);
+  if (threadIdx.x == 0) sc->red[slot] = s;
+}
+
+template <typename S>
+__global__ void k_vec_to_caller(int nc, int np, const int* __restrict__ cam_c2i, const int* __restrict__ pt_c2i,
+                                const S* __restrict__ in, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ncam = 9 * (int64_t)nc;
+  if (i < ncam) {
+    out[i] = (double)in[9 * (size_t)cam_c2i[i / 9] + i % 9];
+  } else if (i < ncam + 3 * (int64_t)np) {
+    const int64_t j = i - ncam;
+    out[i] = (double)in[ncam + 3 * (size_t)pt_c2i[j / 3] + j % 3];
+  }
+}
+
+template <typename S>
+__global__ void k_vec_from_caller(int nc, int np, const int* __restrict__ cam_c2i, const int* __restrict__ pt_c2i,
+                                  const double* __restrict__ in, S* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ncam = 9 * (int64_t)nc;
+  if (i < ncam) {
+    out[9 * (size_t)cam_c2i[i / 9] + i % 9] = (S)in[i];
+  } else if (i < ncam + 3 * (int64_t)np) {
+    const int64_t j = i - ncam;
+    out[ncam + 3 * (size_t)pt_c2i[j / 3] + j % 3] = (S)in[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers.
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int threads) {
+  return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+static inline unsigned vec_grid(int64_t n) { return (unsigned)std::min<int64_t>(nblk(n, 256), 1024); }
+
+template <typename S>
+static void block_jacobi_t(caspar_ba* h, double lambda) {
+  hipStream_t st = h->stream;
+  if (h->nc) {
+    k_bj_cams<S><<<nblk(h->nc, 64), 64, 0, st>>>(h->nc, h->Hcc, (const S*)h->vec.D, lambda, (S*)h->Mc);
+    CBA_LAUNCHED();
+  }
+  if (h->np) {
+    k_bj_points<S><<<nblk(h->np, 256), 256, 0, st>>>(h->np, h->Hpp, (const S*)h->vec.D + 9 * (size_t)h->nc,
+                                                     lambda, (S*)h->Mp);
+    CBA_LAUNCHED();
+  }
+}
+
+void run_block_jacobi(caspar_ba* h, double lambda) {
+  if (h->bj_lambda == lambda) return;
+  if (h->prec == CASPAR_FP64)
+    block_jacobi_t<double>(h, lambda);
+  else
+    block_jacobi_t<float>(h, lambda);
+  h->bj_lambda = lambda;
+}
+
+void run_bj_apply(caspar_ba* h, const void* r, void* z) {
+  const int64_t nb = (int64_t)h->nc + h->np;
+  if (nb == 0) return;
+  if (h->prec == CASPAR_FP64)
+    k_bj_apply<double><<<nblk(nb, 256), 256, 0, h->stream>>>(h->nc, h->np, (const double*)h->Mc,
+                                                             (const double*)h->Mp, (const double*)r, (double*)z);
+  else
+    k_bj_apply<float><<<nblk(nb, 256), 256, 0, h->stream>>>(h->nc, h->np, (const float*)h->Mc,
+                                                            (const float*)h->Mp, (const float*)r, (float*)z);
+  CBA_LAUNCHED();
+}
+
+template <typename S>
+static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double tol, int max_iters,
+                 int check_every, double* rel_resid) {
+  hipStream_t st = h->stream;
+  const int64_t nb = (int64_t)h->nc + h->np;
+  const int64_t N = h->N;
+  S* x = (S*)h->vec.x;
+  S* r = (S*)h->vec.r;
+  S* z = (S*)h->vec.z;
+  S* p = (S*)h->vec.p;
+  S* w = (S*)h->vec.w;
+  const S* Mc = (const S*)h->Mc;
+  const S* Mp = (const S*)h->Mp;
+  run_block_jacobi(h, lambda);
+  const unsigned vg = vec_grid(std::max<int64_t>(nb, 1));
+  k_pcg_init<S><<<vg, 256, 0, st>>>(h->nc, h->np, Mc, Mp, b, negate ? -1.0 : 1.0, x, r, z, p, h->partials);
+  CBA_LAUNCHED();
+  k_pcg_scalar0<<<1, 1024, 0, st>>>((int)vg, h->partials, tol, max_iters, h->scal);
+  CBA_LAUNCHED();
+  const unsigned pg = vec_grid(std::max<int64_t>(N, 1));
+  check_every = std::max(1, check_every);
+  DevScalars s = read_scalars(h);
+  int launched = 0;
+  while (!s.done && launched <= max_iters) {
+    for (int k = 0; k < check_every; ++k) {
+      run_matvec(h, lambda, p, w, true);
+      k_pcg_update<S><<<vg, 256, 0, st>>>(h->nc, h->np, Mc, Mp, x, r, z, p, w, h->scal, h->partials);
+      CBA_LAUNCHED();
+      k_pcg_scalar1<<<1, 1024, 0, st>>>((int)vg, h->partials, h->scal);
+      CBA_LAUNCHED();
+      k_pcg_p<S><<<pg, 256, 0, st>>>(N, z, p, h->scal);
+      CBA_LAUNCHED();
+    }
+    launched += check_every;
+    s = read_scalars(h);
+  }
+  if (!s.done) fail(CASPAR_ENUMERIC, "internal: PCG did not reach its stop condition");
+  if (rel_resid) *rel_resid = s.bb > 0.0 ? std::sqrt(std::max(s.rr, 0.0) / s.bb) : 0.0;
+  return s.iter;
+}
+
+int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double tol, int max_iters,
+            int check_every, void* x, double* rel_resid) {
+  (void)x;
+  if (h->prec == CASPAR_FP64)
+    return pcg_t<double>(h, lambda, (const double*)b, negate_b, tol, max_iters, check_every, rel_resid);
+  return pcg_t<float>(h, lambda, (const float*)b, negate_b, tol, max_iters, check_every, rel_resid);
+}
+
+double run_dot(caspar_ba* h, const void* a, const void* b, const void* e) {
+  const int64_t N = h->N;
+  if (N == 0) return 0.0;
+  const unsigned g = vec_grid(N);
+  if (h->prec == CASPAR_FP64)
+    k_dot<double><<<g, 256, 0, h->stream>>>(N, (const double*)a, (const double*)b, (const double*)e, h->partials);
+  else
+    k_dot<float><<<g, 256, 0, h->stream>>>(N, (const float*)a, (const float*)b, (const float*)e, h->partials);
+  CBA_LAUNCHED();
+  k_reduce_partials<<<1, 1024, 0, h->stream>>>((int)g, h->partials, 0, h->scal, 2);
+  CBA_LAUNCHED();
+  return read_scalars(h).red[2];
+}
+
+double run_absmax(caspar_ba* h, const void* a) {
+  const int64_t N = h->N;
+  if (N == 0) return 0.0;
+  const unsigned g = vec_grid(N);
+  if (h->prec == CASPAR_FP64)
+    k_absmax<double><<<g, 256, 0, h->stream>>>(N, (const double*)a, h->partials);
+  else
+    k_absmax<float><<<g, 256, 0, h->stream>>>(N, (const float*)a, h->partials);
+  CBA_LAUNCHED();
+  k_reduce_partials<<<1, 1024, 0, h->stream>>>((int)g, h->partials, 1, h->scal, 3);
+  CBA_LAUNCHED();
+  return read_scalars(h).red[3];
+}
+
+void run_to_caller_vector(caspar_ba* h, const void* in, double* out) {
+  const int64_t N = h->N;
+  if (N == 0) return;
+  if (h->prec == CASPAR_FP64)
+    k_vec_to_caller<double><<<nblk(N, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam_c2i, h->pt_c2i,
+                                                                 (const double*)in, out);
+  else
+    k_vec_to_caller<float><<<nblk(N, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam_c2i, h->pt_c2i,
+                                                                (const float*)in, out);
+  CBA_LAUNCHED();
+}
+
+void run_from_caller_vector(caspar_ba* h, const double* in, void* out) {
+  const int64_t N = h->N;
+  if (N == 0) return;
+  if (h->prec == CASPAR_FP64)
+    k_vec_from_caller<double><<<nblk(N, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam_c2i, h->pt_c2i, in,
+                                                                   (double*)out);
+  else
+    k_vec_from_caller<float><<<nblk(N, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam_c2i, h->pt_c2i, in,
+                                                                  (float*)out);
+  CBA_LAUNCHED();
+}
+
+void run_zero(caspar_ba* h, void* v, size_t count) {
+  if (count) CBA_HIP(hipMemsetAsync(v, 0, count * scalar_bytes(h->prec), h->stream));
+}
+
+}  // namespace cba

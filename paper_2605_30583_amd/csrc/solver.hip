@@ -1,0 +1,317 @@
+// Levenberg-Marquardt driver (Section V: gain-ratio damping update after
+// Madsen et al., tangent-space retraction, normal equations solved by
+// block-Jacobi PCG without a Schur reduction), the parity hooks and the
+// implicit adjoint of the optimum.
+//
+// One LM iteration:
+//   solve (J^T J + lambda D) delta = -g by PCG
+//   pred = 1/2 (b^T delta + delta^T r_pcg + lambda delta^T D delta), b = -g
+//   rho  = (F - F(theta (+) delta)) / pred
+//   rho > 0 and pred > 0: accept, relinearise,
+//                         lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2
+//   otherwise:            lambda *= nu, nu *= 2
+//   lambda clamped to [lambda_min, lambda_max].
+#include <chrono>
+#include <cmath>
+#include <limits>
+
+#include "common.hpp"
+#include "model.hpp"
+
+namespace cba {
+
+// Right-hand side of the adjoint: caller gradients -> internal tangent order.
+// Cameras: d/d(angle-axis) -> d/d(right perturbation) with J_r^-1(w)^T.
+template <typename S>
+__global__ void k_adjoint_rhs(int nc, int np, const double* __restrict__ cam, const int* __restrict__ cam_c2i,
+                              const int* __restrict__ pt_c2i, const double* __restrict__ gc,
+                              const double* __restrict__ gp, S* __restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nc) {
+    const int ci = cam_c2i[i];
+    S* o = v + 9 * (size_t)ci;
+    if (!gc) {
+      for (int k = 0; k < 9; ++k) o[k] = (S)0;
+      return;
+    }
+    const double* g = gc + 9 * (size_t)i;
+    const double* row = cam + (size_t)ci * kCamStride;
+    double R[9], w[3], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = row[k];
+    so3_log(R, w);
+    so3_grad_to_tangent(w, g, t);
+    for (int k = 0; k < 3; ++k) o[k] = (S)t[k];
+    for (int k = 3; k < 9; ++k) o[k] = (S)g[k];
+  } else if (i < (int64_t)nc + np) {
+    const int64_t p = i - nc;
+    S* o = v + 9 * (size_t)nc + 3 * (size_t)pt_c2i[p];
+    for (int k = 0; k < 3; ++k) o[k] = gp ? (S)gp[3 * p + k] : (S)0;
+  }
+}
+
+// dL/dpx_o = J_o v in caller order.
+template <typename S>
+__global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
+                              const void* __restrict__ J, int no_pad, const S* __restrict__ v, int nc,
+                              const int* __restrict__ s2c, double* __restrict__ out) {
+  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (t >= n_tiles) return;
+  const Tile tl = tiles[t];
+  if (lane >= tile_nobs(tl.info)) return;
+  const int o = tl.obs_begin + lane;
+  const uint32_t m = meta[o];
+  const int ci = (int)(m & ((1u << kCamBits) - 1));
+  const int pi = tl.pt_begin + (int)(m >> kCamBits);
+  S col[12][2];
+  JStore<S>::load(J, no_pad, o, col);
+  double q0 = 0.0, q1 = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    const double x = v[9 * (size_t)ci + k];
+    q0 = fma((double)col[k][0], x, q0);
+    q1 = fma((double)col[k][1], x, q1);
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double x = v[9 * (size_t)nc + 3 * (size_t)pi + k];
+    q0 = fma((double)col[9 + k][0], x, q0);
+    q1 = fma((double)col[9 + k][1], x, q1);
+  }
+  const size_t c = (size_t)s2c[o];
+  out[2 * c] = q0;
+  out[2 * c + 1] = q1;
+}
+
+static inline unsigned nblk(int64_t n, int threads) {
+  return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+static void ensure_linearized(caspar_ba* h) {
+  if (!h->linearized) run_linearize(h);
+}
+
+static void check_device(caspar_ba* h) {
+  int dev = -1;
+  CBA_HIP(hipGetDevice(&dev));
+  if (dev != h->device) CBA_HIP(hipSetDevice(h->device));
+}
+
+static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_solve_stats* stats,
+                       caspar_iter_record* hist) {
+  caspar_solve_opts o;
+  caspar_default_solve_opts(&o);
+  if (opts_in) o = *opts_in;
+  CBA_REQUIRE(o.max_lm_iters >= 0 && o.max_pcg_iters >= 0, "negative iteration limit");
+  CBA_REQUIRE(o.lambda0 > 0.0 && o.lambda_min > 0.0 && o.lambda_max >= o.lambda_min, "bad damping options");
+  CBA_REQUIRE(o.pcg_tol >= 0.0, "bad PCG tolerance");
+  const auto t_start = std::chrono::steady_clock::now();
+  ensure_linearized(h);
+  if (!std::isfinite(h->cost)) fail(CASPAR_ENUMERIC, "initial cost is not finite");
+  const double F0 = h->cost;
+  const double g0 = h->gmax;
+  double lam = std::min(std::max(o.lambda0, o.lambda_min), o.lambda_max);
+  double nu = 2.0;
+  int iters = 0, accepted = 0, pcg_total = 0, reason = 0;
+  for (int it = 0; it < o.max_lm_iters; ++it) {
+    if (h->gmax <= o.grad_tol * std::max(1.0, g0)) {
+      reason = 1;
+      break;
+    }
+    if (h->cost <= o.min_cost) {
+      reason = 2;
+      break;
+    }
+    double rel = 0.0;
+    const int k = run_pcg(h, lam, h->vec.g, true, o.pcg_tol, o.max_pcg_iters, o.pcg_check_every, nullptr, &rel);
+    pcg_total += k;
+    // pred = 1/2 (-g^T x + x^T r + lambda x^T D x)
+    const double gx = run_dot(h, h->vec.g, h->vec.x, nullptr);
+    const double xr = run_dot(h, h->vec.x, h->vec.r, nullptr);
+    const double xDx = run_dot(h, h->vec.x, h->vec.x, h->vec.D);
+    const double pred = 0.5 * (-gx + xr + lam * xDx);
+    run_retract(h, h->vec.x);
+    const double Ft = run_cost(h, h->cam_trial, h->X_trial, false);
+    const double F = h->cost;
+    const double rho = (pred > 0.0 && std::isfinite(Ft)) ? (F - Ft) / pred
+                                                         : -std::numeric_limits<double>::infinity();
+    const double lam_used = lam;
+    const bool acc = rho > 0.0;
+    if (acc) {
+      std::swap(h->cam, h->cam_trial);
+      std::swap(h->X, h->X_trial);
+      h->linearized = false;
+      run_linearize(h);
+      lam *= std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * rho - 1.0, 3));
+      nu = 2.0;
+      ++accepted;
+    } else {
+      lam *= nu;
+      nu = std::min(2.0 * nu, 1152921504606846976.0);  // 2^60
+    }
+    lam = std::min(std::max(lam, o.lambda_min), o.lambda_max);
+    if (hist) {
+      caspar_iter_record& r = hist[it];
+      r.cost = h->cost;
+      r.trial_cost = Ft;
+      r.lambda = lam_used;
+      r.rho = rho;
+      r.pred = pred;
+      r.pcg_rel_resid = rel;
+      r.accepted = acc ? 1 : 0;
+      r.pcg_iters = k;
+    }
+    ++iters;
+  }
+  if (stats) {
+    stats->lm_iters = iters;
+    stats->accepted = accepted;
+    stats->pcg_iters_total = pcg_total;
+    stats->stop_reason = reason;
+    stats->initial_cost = F0;
+    stats->final_cost = h->cost;
+    stats->final_lambda = lam;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+}
+
+template <typename S>
+static void adjoint_rhs_t(caspar_ba* h, const double* gc, const double* gp) {
+  const int64_t n = (int64_t)h->nc + h->np;
+  if (n == 0) return;
+  k_adjoint_rhs<S><<<nblk(n, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam, h->cam_c2i, h->pt_c2i, gc, gp,
+                                                         (S*)h->vec.v);
+  CBA_LAUNCHED();
+}
+
+template <typename S>
+static void adjoint_obs_t(caspar_ba* h, double* out) {
+  if (h->n_tiles == 0) return;
+  k_adjoint_obs<S><<<nblk((int64_t)h->n_tiles * kWave, 256), 256, 0, h->stream>>>(
+      h->n_tiles, h->tiles, h->meta, h->J, h->no_pad, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+  CBA_LAUNCHED();
+}
+
+}  // namespace cba
+
+using namespace cba;
+
+#define CBA_API_BEGIN try {
+#define CBA_API_END                  \
+  }                                  \
+  catch (const Error& e) {           \
+    set_last_error(e.msg);           \
+    return e.status;                 \
+  }                                  \
+  catch (const std::exception& e) {  \
+    set_last_error(e.what());        \
+    return CASPAR_EHIP;              \
+  }                                  \
+  set_last_error("");                \
+  return CASPAR_OK;
+
+extern "C" {
+
+int caspar_ba_solve(caspar_ba* h, const caspar_solve_opts* opts, caspar_solve_stats* stats,
+                    caspar_iter_record* history) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  check_device(h);
+  solve_impl(h, opts, stats, history);
+  CBA_API_END
+}
+
+int caspar_ba_linearize(caspar_ba* h, double* cost, double* resid, double* jac_cam, double* jac_pt,
+                        double* grad, double* diag) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  check_device(h);
+  h->linearized = false;
+  run_linearize(h);
+  if (resid || jac_cam || jac_pt) run_export_linearization(h, resid, jac_cam, jac_pt);
+  if (grad) run_to_caller_vector(h, h->vec.g, grad);
+  if (diag) run_to_caller_vector(h, h->vec.D, diag);
+  if (cost) *cost = h->cost;
+  sync(h);
+  CBA_API_END
+}
+
+int caspar_ba_matvec(caspar_ba* h, double lambda, const double* p, double* w, double* pAp) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(h->N == 0 || (p && w), "p or w is NULL");
+  CBA_REQUIRE(std::isfinite(lambda) && lambda >= 0.0, "lambda must be finite and >= 0");
+  check_device(h);
+  ensure_linearized(h);
+  run_from_caller_vector(h, p, h->vec.v);
+  run_matvec(h, lambda, h->vec.v, h->vec.w, false);
+  run_to_caller_vector(h, h->vec.w, w);
+  const DevScalars s = read_scalars(h);
+  if (pAp) *pAp = s.pAp;
+  CBA_API_END
+}
+
+int caspar_ba_block_jacobi_apply(caspar_ba* h, double lambda, const double* r, double* z) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(h->N == 0 || (r && z), "r or z is NULL");
+  CBA_REQUIRE(std::isfinite(lambda) && lambda >= 0.0, "lambda must be finite and >= 0");
+  check_device(h);
+  ensure_linearized(h);
+  run_block_jacobi(h, lambda);
+  run_from_caller_vector(h, r, h->vec.v);
+  run_bj_apply(h, h->vec.v, h->vec.z);
+  run_to_caller_vector(h, h->vec.z, z);
+  sync(h);
+  CBA_API_END
+}
+
+int caspar_ba_pcg(caspar_ba* h, double lambda, const double* b, double tol, int32_t max_iters, double* x,
+                  int32_t* iters, double* rel_resid) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(h->N == 0 || (b && x), "b or x is NULL");
+  CBA_REQUIRE(std::isfinite(lambda) && lambda >= 0.0 && tol >= 0.0 && max_iters >= 0, "bad PCG arguments");
+  check_device(h);
+  ensure_linearized(h);
+  run_from_caller_vector(h, b, h->vec.v);
+  double rel = 0.0;
+  const int k = run_pcg(h, lambda, h->vec.v, false, tol, max_iters, 4, nullptr, &rel);
+  run_to_caller_vector(h, h->vec.x, x);
+  sync(h);
+  if (iters) *iters = k;
+  if (rel_resid) *rel_resid = rel;
+  CBA_API_END
+}
+
+int caspar_ba_cost_fp64(caspar_ba* h, double* cost) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr && cost != nullptr, "NULL argument");
+  check_device(h);
+  *cost = run_cost(h, h->cam, h->X, true);
+  CBA_API_END
+}
+
+int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points, double lambda_adj,
+                       double pcg_tol, int32_t max_pcg_iters, double* grad_obs_px, int32_t* pcg_iters) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(h->no == 0 || grad_obs_px != nullptr, "grad_obs_px is NULL");
+  CBA_REQUIRE(std::isfinite(lambda_adj) && lambda_adj > 0.0, "lambda_adj must be finite and > 0");
+  CBA_REQUIRE(pcg_tol >= 0.0 && max_pcg_iters >= 0, "bad PCG arguments");
+  check_device(h);
+  ensure_linearized(h);
+  if (h->prec == CASPAR_FP64)
+    adjoint_rhs_t<double>(h, grad_cams, grad_points);
+  else
+    adjoint_rhs_t<float>(h, grad_cams, grad_points);
+  double rel = 0.0;
+  const int k = run_pcg(h, lambda_adj, h->vec.v, false, pcg_tol, max_pcg_iters, 4, nullptr, &rel);
+  if (h->prec == CASPAR_FP64)
+    adjoint_obs_t<double>(h, grad_obs_px);
+  else
+    adjoint_obs_t<float>(h, grad_obs_px);
+  sync(h);
+  if (pcg_iters) *pcg_iters = k;
+  CBA_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+"""Writes tests/golden/lm_reference.json: the oracle's Levenberg-Marquardt
+results on the tiny and medium synthetic workloads.
+
+Calls only synth/ and oracle/ (exact Schur-complement steps, float64).
+Run from the repository root:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import camera, lm  # noqa: E402
+from synth import scene_config  # noqa: E402
+
+RUNS = {"tiny": 20, "medium": 30}
+
+
+def main():
+    out = {"source": "oracle.lm.solve with exact Schur-complement steps (float64); lambda0 1e-2; "
+                     "observed pixels = oracle.camera.project(true parameters) + the scene's noise",
+           "runs": {}}
+    for name, iters in RUNS.items():
+        sc = scene_config(name)
+        st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
+        px = camera.project(st_true, sc.obs_cam, sc.obs_pt) + sc.noise
+        st = camera.State.from_bal(sc.cams_init, sc.points_init)
+        t = time.time()
+        res = lm.solve(st, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=iters, inner="schur"))
+        out["runs"][name] = {
+            "max_iters": iters,
+            "initial_cost": res.initial_cost,
+            "final_cost": res.final_cost,
+            "stop_reason": res.stop_reason,
+            "accepted": [bool(h.accepted) for h in res.history],
+            "costs": [h.cost for h in res.history],
+            "lambdas": [h.lam for h in res.history],
+            "predicted_pixels_sample": camera.project(res.state, sc.obs_cam[:64], sc.obs_pt[:64]).tolist(),
+            "oracle_seconds": time.time() - t,
+        }
+        print(name, res.initial_cost, res.final_cost, f"{time.time() - t:.1f}s", flush=True)
+    path = os.path.join(ROOT, "tests", "golden", "lm_reference.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()
