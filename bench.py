@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the bundle-adjustment hot path on one MI355X.
+
+One step = one Levenberg-Marquardt iteration of the whole hot path on the
+synthetic BAL-shaped workload: linearisation (residuals, Jacobian blocks,
+cost, gradient, block sums), block-Jacobi preconditioner, the PCG solve
+with the fused normal-equation products, retraction and trial cost, and the
+accept/reject update.  W untimed iterations run first (from the initial
+values), then the parameters are reset and exactly K iterations are timed
+(early stopping off), with inputs resident in HBM.
+
+Printed: one JSON line with LM iterations/s (value), the roofline of the
+fused product (its average duration measured with HIP events on the
+library's stream during the timed solve), the float64 plain solve beside the
+float32-mixed one with the cost error between them, the implicit-adjoint
+backward time, and the float64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed LM iterations")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed LM iterations")
+    ap.add_argument("--workload", default="large_zipf",
+                    choices=["tiny", "medium", "bal1700", "large_zipf"])
+    ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
+    ap.add_argument("--pcg-tol", type=float, default=1e-3, help="PCG relative tolerance (paper: 1e-3)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 plain solve beside the mixed one")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-points", type=int, default=150_000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("matvec.hip", "model.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2605_30583_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str, precision: str):
+    """HBM bytes per fused-product launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(PROFILES, f"matvec_{workload}_{precision}_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, n_points: int, pcg_tol: float):
+    """The oracle (float64, NumPy/SciPy, unchanged) on a bounded sample: the
+    first n_points points with all their observations, one LM iteration with
+    the same PCG inner solve; scaled to the full workload by observations."""
+    from oracle import camera, lm
+    m = sc.obs_pt < n_points
+    oc, op = sc.obs_cam[m], sc.obs_pt[m]
+    st_true = camera.State.from_bal(sc.cams_true, sc.points_true[:n_points])
+    px = camera.project(st_true, oc, op) + sc.noise[m]
+    st = camera.State.from_bal(sc.cams_init, sc.points_init[:n_points])
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    t = time.perf_counter()
+    lm.solve(st, oc, op, px, lm.LMOptions(max_iters=1, inner="pcg", pcg_tol=pcg_tol))
+    dt = time.perf_counter() - t
+    frac = float(m.sum()) / sc.n_obs
+    return {
+        "value": frac / dt,
+        "unit": "LM iterations/s",
+        "cores": int(blas),
+        "kind": "oracle",
+        "sample": (f"1 LM iteration (PCG inner, tol {pcg_tol:g}) on the first {n_points} points and their "
+                   f"{int(m.sum())} observations ({100 * frac:.2f}% of the workload) in {dt:.1f} s; rate scaled "
+                   f"by the observation fraction; sparse products run on one thread, BLAS on {blas}"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (no multi-GPU path in this build)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_30583_amd import FP32_MIXED, FP64, BundleAdjuster, SolveOptions, project
+    from synth import scene_config
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if a.copy_calibration_mib > 0:
+        n = a.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n} bytes read, {n} bytes written")
+        del src, dst
+    t = time.time()
+    sc = scene_config(a.workload)
+    log(f"scene {a.workload}: {sc.n_cams} cameras, {sc.n_points} points, {sc.n_obs} observations "
+        f"({time.time() - t:.1f}s)")
+
+    def t64(x):
+        return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
+
+    def t32(x):
+        return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).to(dev)
+
+    oc, op = t32(sc.obs_cam), t32(sc.obs_pt)
+    px = project(t64(sc.cams_true), t64(sc.points_true), oc, op) + t64(sc.noise)
+    cams0, pts0 = t64(sc.cams_init), t64(sc.points_init)
+    prec = FP32_MIXED if a.precision == "fp32_mixed" else FP64
+
+    def timed_solve(precision, label):
+        t = time.time()
+        ba = BundleAdjuster(cams0, pts0, oc, op, px, precision)
+        torch.cuda.synchronize()
+        log(f"{label}: create {time.time() - t:.2f}s, layout {ba.layout_info()}")
+        if a.warmup > 0:
+            ba.solve(SolveOptions(max_lm_iters=a.warmup, pcg_tol=a.pcg_tol))
+            ba.set_params(cams0, pts0)
+        opts = SolveOptions(max_lm_iters=a.steps, pcg_tol=a.pcg_tol, grad_tol=0.0, min_cost=0.0)
+        ba.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ba.solve(opts, history=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tim = ba.get_timing()
+        ba.set_timing(False)
+        log(f"{label}: {st['lm_iters']} LM iterations in {dt:.3f}s, PCG {st['pcg_iters_total']}, "
+            f"F {st['initial_cost']:.6e} -> {st['final_cost']:.6e}")
+        return ba, st, dt, tim
+
+    ba, st, dt, tim = timed_solve(prec, a.precision)
+    iters = st["lm_iters"]
+    value = iters / dt
+    mv_avg_ms = tim["matvec_ms"] / max(1, tim["matvec_launches"])
+    achieved = tim["matvec_bytes"] / (mv_avg_ms * 1e-3) / 1e9 if tim["matvec_launches"] else None
+    f_primary = ba.cost_fp64()
+
+    extra = {}
+    if prec == FP32_MIXED and not a.no_fp64:
+        ba64, st64, dt64, tim64 = timed_solve(FP64, "fp64")
+        f64 = ba64.cost_fp64()
+        mv64 = tim64["matvec_ms"] / max(1, tim64["matvec_launches"])
+        extra["fp64"] = {
+            "lm_iters_per_s": st64["lm_iters"] / dt64,
+            "final_cost": f64,
+            "pcg_iters_total": st64["pcg_iters_total"],
+            "matvec_avg_ms": mv64,
+            "matvec_gbs": tim64["matvec_bytes"] / (mv64 * 1e-3) / 1e9 if tim64["matvec_launches"] else None,
+        }
+        extra["fp32_mixed_cost_rel_error_vs_fp64"] = (f_primary - f64) / f64
+        del ba64
+        torch.cuda.empty_cache()
+
+    if not a.no_adjoint:
+        _, pts = ba.get_params()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = ba.backward(None, 2.0 * pts, lambda_adj=1e-4, pcg_tol=1e-6, max_pcg_iters=500)
+        torch.cuda.synchronize()
+        extra["adjoint"] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": ba.last_backward_iters,
+                            "loss": "sum of squared optimal point coordinates", "grad_norm": float(g.norm())}
+
+    line = {
+        "metric": "LM iterations/sec + PCG matvec HBM GB/s, FP32-mixed vs FP64 at stated cost error",
+        "value": value,
+        "unit": "LM iterations/s",
+        "n_gpus": 1,
+        "steps": iters,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / max(1, iters),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == FP32_MIXED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": a.workload,
+            "n_cams": sc.n_cams, "n_points": sc.n_points, "n_obs": sc.n_obs,
+            "precision": a.precision, "pcg_tol": a.pcg_tol,
+            "pcg_iters_per_lm_iter": st["pcg_iters_total"] / max(1, iters),
+            "accepted": st["accepted"],
+            "final_cost_fp64_eval": f_primary,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": counter_traffic(a.workload, a.precision),
+            "kernel": "k_matvec",
+            "avg_ms": mv_avg_ms,
+            "launches": tim["matvec_launches"],
+            "algorithmic_bytes_per_launch": tim["matvec_bytes"],
+        },
+    }
+    line.update(extra)
+    if not a.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(sc, a.cpu_sample_points, a.pcg_tol)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,20 @@ CASPAR_API int caspar_project(int32_t n_cams, int32_t n_points, int64_t n_obs, c
 CASPAR_API int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* cold_obs, int64_t* n_tiles,
                           int32_t* matvec_groups);
 
+/* Kernel timing for roofline reporting.  While enabled, every launch of the
+ * fused normal-equation product made by solve/pcg/backward/matvec is
+ * bracketed by HIP events on the handle's stream; launches that found the
+ * PCG already finished (no work) are not counted. */
+typedef struct caspar_timing {
+  int64_t matvec_launches;  /* fused-product launches that did work */
+  double matvec_ms;         /* summed duration of those launches (event time) */
+  double matvec_bytes;      /* algorithmic bytes of one launch (see DESIGN notes) */
+} caspar_timing;
+
+/* enable != 0 starts (and zeroes) the counters; 0 stops them. */
+CASPAR_API int caspar_ba_set_timing(caspar_ba* h, int enable);
+CASPAR_API int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out);
+
 CASPAR_API void caspar_ba_destroy(caspar_ba* h);
 
 /* Message of the last failed call on this thread ("" if none). */

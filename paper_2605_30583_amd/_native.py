@@ -30,6 +30,10 @@ class IterRecord(C.Structure):
                 ("pcg_iters", C.c_int32)]
 
 
+class Timing(C.Structure):
+    _fields_ = [("matvec_launches", C.c_int64), ("matvec_ms", C.c_double), ("matvec_bytes", C.c_double)]
+
+
 # (name, restype, argtypes) for every exported function
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
@@ -52,6 +56,8 @@ SIGNATURES = [
     ("caspar_project", C.c_int, [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
     ("caspar_ba_layout_info", C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_int32)]),
+    ("caspar_ba_set_timing", C.c_int, [_P, C.c_int]),
+    ("caspar_ba_get_timing", C.c_int, [_P, C.POINTER(Timing)]),
     ("caspar_ba_destroy", None, [_P]),
     ("caspar_last_error", C.c_char_p, []),
 ]

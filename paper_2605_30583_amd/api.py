@@ -193,6 +193,14 @@ class BundleAdjuster:
         self.last_backward_iters = it.value
         return out
 
+    def set_timing(self, enable: bool):
+        check(self._lib.caspar_ba_set_timing(self._h, 1 if enable else 0))
+
+    def get_timing(self):
+        t = _native.Timing()
+        check(self._lib.caspar_ba_get_timing(self._h, C.byref(t)))
+        return {"matvec_launches": t.matvec_launches, "matvec_ms": t.matvec_ms, "matvec_bytes": t.matvec_bytes}
+
     def layout_info(self):
         k, cold, tiles, groups = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
         check(self._lib.caspar_ba_layout_info(self._h, C.byref(k), C.byref(cold), C.byref(tiles), C.byref(groups)))

@@ -48,14 +48,28 @@ constexpr int kCamStride = 16;       // doubles per camera row: R(9) t(3) f k1 k
 constexpr int kCamChunk = 2048;      // camera-major entries per linearisation chunk
 constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
 constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
+constexpr int kColdRow = 10;         // doubles per cold-camera row (9 sums, padded to 80 bytes)
 constexpr int kMvThreads = 1024;     // fused product: 16 waves per workgroup
 constexpr int kMvWaves = kMvThreads / kWave;
 constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
-constexpr int kMaxHot = kLdsBudget / (9 * 8);
+constexpr int kMaxHot = kLdsBudget / (9 * 8);  // 2048 cameras with float64 sums
 constexpr int kMaxPartials = 4096;   // per-workgroup partial slots
 constexpr int kPartialWidth = 4;     // doubles per partial slot
 constexpr int kCamBits = 25;         // meta: camera id bits; local point in bits 25..30
 constexpr int kNumCUs = 256;
+
+// Padded camera row of the fused product's input vector: 10 doubles (5 x 16 B)
+// or 12 floats (3 x 16 B).
+template <typename S>
+struct CamPad;
+template <>
+struct CamPad<double> {
+  static constexpr int n = 10;
+};
+template <>
+struct CamPad<float> {
+  static constexpr int n = 12;
+};
 
 // Wave tile: a run of whole points (or one slice of a point with more than
 // kTileMax observations) covering <= kTileMax consecutive observations.
@@ -112,6 +126,7 @@ struct Vectors {
 }  // namespace cba
 
 struct caspar_ba {
+  ~caspar_ba();
   int nc = 0, np = 0;
   int no = 0;
   int prec = CASPAR_FP64;
@@ -124,11 +139,12 @@ struct caspar_ba {
   int G = 0;              // workgroups of the fused product
   int n_tiles = 0;
   int n_cold = 0;         // observations of cameras >= K
+  int n_cold_rows = 0;    // distinct (tile, camera >= K) pairs: rows of the fused product
   int n_split_tiles = 0;
   int n_split_pts = 0;
   int n_orphan_pts = 0;   // points without observations (internal ids [0, n_orphan))
   int n_chunks = 0;
-  int no_pad = 0;         // observations rounded up to 64
+  int no_pad = 0;         // observations rounded up to the Jacobian block
 
   // parameters (float64, internal order)
   double* cam = nullptr;        // [nc][16]
@@ -159,12 +175,14 @@ struct caspar_ba {
   double* chunk_rows = nullptr; // [n_chunks][54]
 
   // fused product side buffers
+  uint8_t* cold_perm = nullptr; // [n_tiles][64] lanes of a tile's cold observations sorted by camera
+  void* p_cam = nullptr;        // [nc][kCamPad] camera part of the product's input, 16-byte rows
   int* cold_list = nullptr;     // cold rows grouped by camera
   int* cold_off = nullptr;      // [nc - K + 1]
-  double* cold_rows = nullptr;  // [n_cold][9]
+  void* cold_rows = nullptr;    // [n_cold][9] accumulator type
   cba::SplitPoint* split_pts = nullptr;
   double* split_rows = nullptr; // [n_split_tiles][9]
-  double* hot_rows = nullptr;   // [G][K][9]
+  void* hot_rows = nullptr;     // [G][K][9] accumulator type
 
   // normal-equation blocks
   double* Hcc = nullptr;        // [nc][45]
@@ -175,6 +193,13 @@ struct caspar_ba {
 
   double* partials = nullptr;   // [kMaxPartials][4]
   cba::DevScalars* scal = nullptr;
+
+  // kernel timing (roofline reporting)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+  int64_t mv_launches = 0;
+  double mv_ms = 0.0;
 
   // state
   bool linearized = false;      // J, g, D, H match the current parameters
@@ -192,7 +217,7 @@ struct Plan {
     size_t off = 0, bytes = 0;
   };
   Region cam, cam_trial, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
-      tiles, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
+      tiles, cold_perm, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
@@ -201,6 +226,10 @@ struct Plan {
 bool make_plan(int nc, int np, int64_t no, int prec, Plan& plan);
 
 inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
+
+// The fused product accumulates camera sums in float64 in both precisions
+// (ds_add_f64 in LDS measured faster than ds_add_f32 on this chip).
+inline size_t acc_bytes(int) { return 8; }
 
 // Launch helpers implemented per translation unit (S = double or float).
 // layout.hip
@@ -223,6 +252,10 @@ double run_absmax(caspar_ba* h, const void* a);
 void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
 void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);
 void run_zero(caspar_ba* h, void* v, size_t count_scalars);
+void timing_mark_start(caspar_ba* h);
+void timing_mark_stop(caspar_ba* h);
+void timing_harvest(caspar_ba* h, int effective);  // after a sync: count the first `effective` launches
+double matvec_algorithmic_bytes(const caspar_ba* h);
 // helpers
 void sync(caspar_ba* h);
 DevScalars read_scalars(caspar_ba* h);

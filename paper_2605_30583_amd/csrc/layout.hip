@@ -55,8 +55,8 @@ static size_t sort_temp_bytes(int64_t no) {
   return std::max(a, b) + (1 << 20);
 }
 
-static int groups_per_cu(int K) {
-  const size_t lds = (size_t)K * 9 * sizeof(double);
+static int groups_per_cu(int K, int prec) {
+  const size_t lds = (size_t)K * 9 * acc_bytes(prec);
   return lds > 80 * 1024 ? 1 : 2;
 }
 
@@ -70,11 +70,11 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
   const size_t nch = prec == CASPAR_FP64 ? 12 : 6;
   const size_t sort_bytes = sort_temp_bytes(no);
   if (sort_bytes == (size_t)-1) return false;
-  const size_t no_pad = align_up((size_t)no, 64);
+  const size_t no_pad = align_up((size_t)no, kJBlock);
   const size_t N = 9 * (size_t)nc + 3 * (size_t)np;
   p = Plan{};
   p.K = std::min(nc, kMaxHot);
-  p.G = groups_per_cu(p.K) * kNumCUs;
+  p.G = groups_per_cu(p.K, prec) * kNumCUs;
   p.max_tiles = (size_t)no / 16 + 8;
   p.max_chunks = (size_t)no / kCamChunk + nc + 1;
   p.max_cold = nc > p.K ? (size_t)((no * (int64_t)(nc - p.K)) / nc + 1) : 0;
@@ -105,6 +105,8 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
                          align_up(sort_bytes) + 8 * (size_t)np + 8 * (size_t)nc + 8192;
   take(p.J, std::max(nch * no_pad * 16, scratch));
   take(p.tiles, p.max_tiles * sizeof(Tile));
+  take(p.cold_perm, nc > p.K ? p.max_tiles * 64 : 64);
+  take(p.p_cam, (size_t)nc * 80);  // 10 doubles or 12 floats per camera
   take(p.cm_pt, (size_t)no * 4);
   take(p.cm_px, (size_t)no * 16);
   take(p.cam_off, ((size_t)nc + 1) * 4);
@@ -113,10 +115,10 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
   take(p.chunk_rows, p.max_chunks * kCamRowWidth * 8);
   take(p.cold_list, p.max_cold * 4 + 4);
   take(p.cold_off, ((size_t)(nc - p.K) + 1) * 4);
-  take(p.cold_rows, p.max_cold * 9 * 8 + 8);
+  take(p.cold_rows, p.max_cold * kColdRow * 8 + 16);
   take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
   take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
-  take(p.hot_rows, (size_t)p.G * p.K * 9 * 8);
+  take(p.hot_rows, (size_t)p.G * p.K * 9 * acc_bytes(prec));
   take(p.Hcc, (size_t)nc * 45 * 8);
   take(p.Hpp, (size_t)np * 6 * 8);
   take(p.Mc, (size_t)nc * 45 * s);
@@ -207,38 +209,8 @@ __global__ void k_fill_cm(int no, const int* __restrict__ cm_obs, const uint64_t
   }
 }
 
-// Cold observations (camera id >= K) per tile.
-__global__ void k_cold_count(int n_tiles, int K, const Tile* __restrict__ tiles,
-                             const uint32_t* __restrict__ meta, int* cnt) {
-  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (t >= n_tiles) return;
-  const Tile tl = tiles[t];
-  const bool cold = lane < tile_nobs(tl.info) &&
-                    (int)(meta[tl.obs_begin + lane] & ((1u << kCamBits) - 1)) >= K;
-  const unsigned long long m = __ballot(cold);
-  if (lane == 0) cnt[t] = __popcll(m);
-}
 
-// Row of each cold observation: tile base + rank among the tile's cold lanes.
-__global__ void k_cold_rows(int n_tiles, int K, const Tile* __restrict__ tiles,
-                            const uint32_t* __restrict__ meta, int* row_of) {
-  const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (t >= n_tiles) return;
-  const Tile tl = tiles[t];
-  const bool act = lane < tile_nobs(tl.info);
-  const bool cold = act && (int)(meta[tl.obs_begin + lane] & ((1u << kCamBits) - 1)) >= K;
-  const unsigned long long m = __ballot(cold);
-  const int rank = __popcll(m & ((1ull << lane) - 1ull));
-  if (act) row_of[tl.obs_begin + lane] = cold ? tl.cold_begin + rank : -1;
-}
 
-__global__ void k_cold_list(int n, int base, const int* __restrict__ cm_obs,
-                            const int* __restrict__ row_of, int* cold_list) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) cold_list[j] = row_of[cm_obs[base + j]];
-}
 
 __global__ void k_cams_from_bal(int nc, const double* __restrict__ bal, const int* __restrict__ c2i,
                                 double* cam) {
@@ -383,7 +355,6 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   uint64_t* keys_b = (uint64_t*)carve(8 * (size_t)no);
   int* vals_a = (int*)carve(4 * (size_t)no);
   int* vals_b = (int*)carve(4 * (size_t)no);
-  int* row_of = (int*)carve(4 * (size_t)no);
   const size_t cub_bytes = sort_temp_bytes(no);
   void* cub_tmp = carve(cub_bytes);
   int* pt_cnt = (int*)carve(4 * (size_t)np);
@@ -536,37 +507,52 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   h2d(h, h->chunk_off, chunk_off);
   h2d(h, h->chunks, chunks);
 
-  // Cold cameras: rows of the fused product and their per-camera lists.
+  // Cold cameras (internal id >= K): inside each tile the observations of
+  // one cold camera share a row of the fused product.  Per tile: the lanes of
+  // its cold observations sorted by camera (then lane), and one row per
+  // distinct cold camera, numbered in that order.  Per camera: its rows.
   h->n_cold = (nc > h->K) ? cam_off[nc] - cam_off[h->K] : 0;
-  if ((size_t)h->n_cold > plan.max_cold) fail(CASPAR_ENOMEM, "internal: cold rows exceed plan");
+  h->n_cold_rows = 0;
   if (h->n_cold > 0) {
-    int* cnt = row_of;  // reuse as per-tile counter first
-    k_cold_count<<<blocks_for((int64_t)h->n_tiles * kWave, 256), 256, 0, st>>>(h->n_tiles, h->K, h->tiles,
-                                                                           h->meta, cnt);
-    CBA_LAUNCHED();
-    std::vector<int> tc = d2h(h, cnt, h->n_tiles);
-    int run = 0;
+    std::vector<uint32_t> meta_h = d2h(h, h->meta, (size_t)no);
+    std::vector<uint8_t> perm((size_t)h->n_tiles * 64, 0);
+    std::vector<std::vector<int>> rows_of(nc - h->K);
+    std::vector<std::pair<int, int>> cl;
+    int run = 0, n_cold_seen = 0;
     for (int t = 0; t < h->n_tiles; ++t) {
+      const int n = tile_nobs(tiles[t].info);
+      cl.clear();
+      for (int lane = 0; lane < n; ++lane) {
+        const int ci = (int)(meta_h[tiles[t].obs_begin + lane] & ((1u << kCamBits) - 1));
+        if (ci >= h->K) cl.emplace_back(ci, lane);
+      }
+      std::sort(cl.begin(), cl.end());
       tiles[t].cold_begin = run;
-      run += tc[t];
+      for (size_t j = 0; j < cl.size(); ++j) {
+        perm[(size_t)t * 64 + j] = (uint8_t)cl[j].second;
+        if (j == 0 || cl[j].first != cl[j - 1].first) rows_of[cl[j].first - h->K].push_back(run++);
+      }
+      n_cold_seen += (int)cl.size();
     }
-    if (run != h->n_cold) fail(CASPAR_EINVAL, "internal: cold count mismatch");
+    if (n_cold_seen != h->n_cold) fail(CASPAR_EINVAL, "internal: cold count mismatch");
+    if ((size_t)run > plan.max_cold) fail(CASPAR_ENOMEM, "internal: cold rows exceed plan");
+    h->n_cold_rows = run;
+    std::vector<int> coff(nc - h->K + 1, 0), clist;
+    clist.reserve(run);
+    for (int c = h->K; c < nc; ++c) {
+      coff[c - h->K + 1] = coff[c - h->K] + (int)rows_of[c - h->K].size();
+      clist.insert(clist.end(), rows_of[c - h->K].begin(), rows_of[c - h->K].end());
+    }
     h2d(h, h->tiles, tiles);
-    k_cold_rows<<<blocks_for((int64_t)h->n_tiles * kWave, 256), 256, 0, st>>>(h->n_tiles, h->K, h->tiles,
-                                                                          h->meta, row_of);
-    CBA_LAUNCHED();
-    k_cold_list<<<blocks_for(h->n_cold, 256), 256, 0, st>>>(h->n_cold, cam_off[h->K], cm_obs, row_of,
-                                                            h->cold_list);
-    CBA_LAUNCHED();
-    std::vector<int> coff(nc - h->K + 1);
-    for (int c = h->K; c <= nc; ++c) coff[c - h->K] = cam_off[c] - cam_off[h->K];
+    h2d(h, h->cold_perm, perm);
     h2d(h, h->cold_off, coff);
+    h2d(h, h->cold_list, clist);
   } else if (no) {
     h2d(h, h->tiles, tiles);
   }
 
   // Fused-product grid.
-  h->G = std::max(1, std::min(groups_per_cu(h->K) * kNumCUs, (h->n_tiles + kMvWaves - 1) / kMvWaves));
+  h->G = std::max(1, std::min(groups_per_cu(h->K, h->prec) * kNumCUs, (h->n_tiles + kMvWaves - 1) / kMvWaves));
 
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);
@@ -575,6 +561,11 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
 }
 
 }  // namespace cba
+
+caspar_ba::~caspar_ba() {
+  for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+}
 
 using namespace cba;
 
@@ -641,7 +632,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->prec = precision;
     h->N = 9 * n_cams + 3 * n_points;
     h->stream = (hipStream_t)hip_stream;
-    h->no_pad = (int)align_up((size_t)n_obs, 64);
+    h->no_pad = (int)align_up((size_t)n_obs, kJBlock);
     h->K = plan.K;
     CBA_HIP(hipGetDevice(&h->device));
     char* ws = (char*)workspace;
@@ -660,6 +651,8 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->px = (double*)(ws + plan.px.off);
     h->J = ws + plan.J.off;
     h->tiles = (Tile*)(ws + plan.tiles.off);
+    h->cold_perm = (uint8_t*)(ws + plan.cold_perm.off);
+    h->p_cam = ws + plan.p_cam.off;
     h->cm_obs = (int*)(ws + plan.cm_obs.off);
     h->cm_pt = (int*)(ws + plan.cm_pt.off);
     h->cm_px = (double*)(ws + plan.cm_px.off);
@@ -669,10 +662,10 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->chunk_rows = (double*)(ws + plan.chunk_rows.off);
     h->cold_list = (int*)(ws + plan.cold_list.off);
     h->cold_off = (int*)(ws + plan.cold_off.off);
-    h->cold_rows = (double*)(ws + plan.cold_rows.off);
+    h->cold_rows = ws + plan.cold_rows.off;
     h->split_pts = (SplitPoint*)(ws + plan.split_pts.off);
     h->split_rows = (double*)(ws + plan.split_rows.off);
-    h->hot_rows = (double*)(ws + plan.hot_rows.off);
+    h->hot_rows = ws + plan.hot_rows.off;
     h->Hcc = (double*)(ws + plan.Hcc.off);
     h->Hpp = (double*)(ws + plan.Hpp.off);
     h->Mc = ws + plan.Mc.off;

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
                                                     const uint32_t* __restrict__ meta,
                                                     const double* __restrict__ px,
                                                     const double* __restrict__ cam,
-                                                    const double* __restrict__ X, void* J, int no_pad,
+                                                    const double* __restrict__ X, void* J,
                                                     S* __restrict__ g, S* __restrict__ D,
                                                     double* __restrict__ Hpp,
                                                     double* __restrict__ split_rows, int nc,
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
       const double2 q = reinterpret_cast<const double2*>(px)[o];
       S r0, r1, col[12][2];
       snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
-      JStore<S>::store(J, no_pad, o, col);
-      cost = fma((double)r0, (double)r0, (double)r1 * (double)r1);
+      JStore<S>::store(J, o, col);
+      cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
       double jp[3][2];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -188,22 +188,29 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
   }
 }
 
-// Per camera: sum the chunk rows into g_c, H_cc and D_c.
+// Per camera (one workgroup): sum the chunk rows into g_c, H_cc and D_c;
+// each wave takes every fourth of the 54 values, lanes stride the chunks.
 template <typename S>
-__global__ void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
-                                const double* __restrict__ rows, S* g, S* D, double* Hcc) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nc * kCamRowWidth) return;
-  const int c = (int)(i / kCamRowWidth), k = (int)(i % kCamRowWidth);
-  double s = 0.0;
-  for (int q = chunk_off[c]; q < chunk_off[c + 1]; ++q) s += rows[(size_t)q * kCamRowWidth + k];
-  if (k < 9) {
-    g[9 * (size_t)c + k] = (S)s;
-  } else {
-    const int h = k - 9;
-    Hcc[45 * (size_t)c + h] = s;
-    for (int d = 0; d < 9; ++d)
-      if (tri9(d, d) == h) D[9 * (size_t)c + d] = (S)clamp_diag(s);
+__global__ __launch_bounds__(256) void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
+                                                       const double* __restrict__ rows, S* g, S* D,
+                                                       double* Hcc) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int q0 = chunk_off[c], q1 = chunk_off[c + 1];
+  for (int k = wv; k < kCamRowWidth; k += 4) {
+    double s = 0.0;
+    for (int q = q0 + lane; q < q1; q += kWave) s += rows[(size_t)q * kCamRowWidth + k];
+    s = wave_sum(s);
+    if (lane == 0) {
+      if (k < 9) {
+        g[9 * (size_t)c + k] = (S)s;
+      } else {
+        const int hidx = k - 9;
+        Hcc[45 * (size_t)c + hidx] = s;
+        for (int d = 0; d < 9; ++d)
+          if (tri9(d, d) == hidx) D[9 * (size_t)c + d] = (S)clamp_diag(s);
+      }
+    }
   }
 }
 
@@ -284,7 +291,7 @@ __global__ void k_retract_points(int np, const double* __restrict__ X, const S* 
 template <typename S>
 __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
                              const double* __restrict__ px, const double* __restrict__ cam,
-                             const double* __restrict__ X, const void* J, int no_pad,
+                             const double* __restrict__ X, const void* J,
                              const int* __restrict__ s2c, double* resid, double* jc, double* jp) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -306,7 +313,7 @@ __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const 
     resid[2 * c + 1] = r1;
   }
   S col[12][2];
-  JStore<S>::load(J, no_pad, o, col);
+  JStore<S>::load(J, o, col);
   if (jc)
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 9; ++j) jc[18 * c + 9 * i + j] = col[j][i];
@@ -334,7 +341,7 @@ static void linearize_t(caspar_ba* h) {
   const unsigned tg = tile_grid(h->n_tiles);
   if (h->n_tiles > 0) {
     k_lin_points<S><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J,
-                                         h->no_pad, g, D, h->Hpp, h->split_rows, h->nc, h->partials);
+                                         g, D, h->Hpp, h->split_rows, h->nc, h->partials);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
     CBA_LAUNCHED();
@@ -355,8 +362,7 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->nc > 0) {
-    k_lin_cam_final<S><<<nblk((int64_t)h->nc * kCamRowWidth, 256), 256, 0, st>>>(h->nc, h->chunk_off,
-                                                                             h->chunk_rows, g, D, h->Hcc);
+    k_lin_cam_final<S><<<h->nc, 256, 0, st>>>(h->nc, h->chunk_off, h->chunk_rows, g, D, h->Hcc);
     CBA_LAUNCHED();
   }
 }
@@ -413,10 +419,10 @@ void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* j
   const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
   if (h->prec == CASPAR_FP64)
     k_export_lin<double><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
-                                                      h->J, h->no_pad, h->obs_s2c, resid, jc, jp);
+                                                      h->J, h->obs_s2c, resid, jc, jp);
   else
     k_export_lin<float><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
-                                                     h->J, h->no_pad, h->obs_s2c, resid, jc, jp);
+                                                     h->J, h->obs_s2c, resid, jc, jp);
   CBA_LAUNCHED();
 }
 

@@ -24,20 +24,84 @@
 
 namespace cba {
 
+// Camera part of p copied to 16-byte aligned rows for vector loads.
 template <typename S>
-__global__ __launch_bounds__(kMvThreads) void k_matvec(
+__global__ void k_pad_cams(int nc, const S* __restrict__ p, S* __restrict__ out, const DevScalars* __restrict__ sc) {
+  if (sc != nullptr && sc->done) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  S* o = out + (size_t)c * CamPad<S>::n;
+#pragma unroll
+  for (int k = 0; k < CamPad<S>::n; ++k) o[k] = k < 9 ? p[9 * (size_t)c + k] : (S)0;
+}
+
+template <typename S>
+__device__ inline void load_cam_row(const S* __restrict__ rows, int c, S* out);
+template <>
+__device__ inline void load_cam_row<double>(const double* __restrict__ rows, int c, double* out) {
+  const double2* r = reinterpret_cast<const double2*>(rows + (size_t)c * CamPad<double>::n);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double2 v = r[i];
+    out[2 * i] = v.x;
+    out[2 * i + 1] = v.y;
+  }
+}
+template <>
+__device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c, float* out) {
+  const float4* r = reinterpret_cast<const float4*>(rows + (size_t)c * CamPad<float>::n);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float4 v = r[i];
+    out[4 * i] = v.x;
+    out[4 * i + 1] = v.y;
+    out[4 * i + 2] = v.z;
+    out[4 * i + 3] = v.w;
+  }
+}
+
+// Launch shape of the fused product per precision: 16 waves per workgroup,
+// and the next tile's Jacobian chunks prefetched while the current tile is
+// computed (float32: 24 extra VGPRs; float64 prefetches only the meta word).
+template <typename S>
+struct MvCfg;
+template <>
+struct MvCfg<float> {
+  static constexpr int threads = 1024;
+  static constexpr bool prefetch_j = true;
+};
+template <>
+struct MvCfg<double> {
+  static constexpr int threads = 1024;
+  static constexpr bool prefetch_j = false;
+};
+
+// Writes one cold row (9 sums, padded to kColdRow doubles: five 16-byte stores).
+__device__ inline void store_cold_row(double* row, const double v[9]) {
+  double2* r = reinterpret_cast<double2*>(row);
+  r[0] = make_double2(v[0], v[1]);
+  r[1] = make_double2(v[2], v[3]);
+  r[2] = make_double2(v[4], v[5]);
+  r[3] = make_double2(v[6], v[7]);
+  r[4] = make_double2(v[8], 0.0);
+}
+
+template <typename S, int THREADS, bool PREFETCH_J>
+__global__ __launch_bounds__(THREADS) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-    const void* __restrict__ J, int no_pad, const S* __restrict__ p, const S* __restrict__ D,
-    double lambda, S* __restrict__ w, int nc, int K, int n_orphan, double* __restrict__ hot_rows,
-    double* __restrict__ cold_rows, double* __restrict__ split_rows, double* __restrict__ partials,
-    const DevScalars* __restrict__ sc) {
-  extern __shared__ double hot[];  // [K][9]
-  __shared__ double red[kMvWaves];
+    const void* __restrict__ J, const S* __restrict__ p_cam, const uint8_t* __restrict__ cold_perm,
+    const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
+    int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
+    double* __restrict__ partials, const DevScalars* __restrict__ sc) {
+  constexpr int WAVES = THREADS / kWave;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* hot = reinterpret_cast<double*>(lds_raw);  // [K][9]
+  __shared__ double red[WAVES];
   if (sc != nullptr && sc->done) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  for (int i = tid; i < K * 9; i += kMvThreads) hot[i] = 0.0;
+  for (int i = tid; i < K * 9; i += THREADS) hot[i] = 0.0;
   __syncthreads();
 
   const S* __restrict__ pp_base = p + 9 * (size_t)nc;
@@ -46,38 +110,67 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(
   double pap = 0.0;
   const int t0 = (int)((int64_t)n_tiles * blockIdx.x / G);
   const int t1 = (int)((int64_t)n_tiles * (blockIdx.x + 1) / G);
-  for (int t = t0 + wv; t < t1; t += kMvWaves) {
-    const Tile tl = tiles[t];
-    const int n = tile_nobs(tl.info);
+
+  // state of the current tile: descriptor, meta word, Jacobian columns
+  int t = t0 + wv;
+  Tile tl{};
+  int n = 0;
+  uint32_t m = 0;
+  S col[12][2];
+  if (t < t1) {
+    tl = tiles[t];
+    n = tile_nobs(tl.info);
+    if (lane < n) {
+      m = meta[tl.obs_begin + lane];
+      JStore<S>::load(J, tl.obs_begin + lane, col);
+    }
+  }
+  for (; t < t1; t += WAVES) {
     const bool act = lane < n;
-    int lp = 100 + lane;
-    int ci = -1;
+    const int ci = act ? (int)(m & ((1u << kCamBits) - 1)) : -1;
+    const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
+    // 1. gathers of the current tile (camera row, point block)
+    S pcv[CamPad<S>::n], pjv[3];
+    if (act) {
+      load_cam_row<S>(p_cam, ci, pcv);
+      const S* pj = pp_base + 3 * (size_t)(tl.pt_begin + lp);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pjv[k] = pj[k];
+    }
+    // 2. prefetch of the next tile, issued after the gathers so that waiting
+    //    for the gathers does not wait for it
+    __builtin_amdgcn_sched_barrier(0);
+    const int tn = t + WAVES;
+    Tile tln{};
+    int nn = 0;
+    uint32_t mn = 0;
+    S coln[12][2];
+    if (tn < t1) {
+      tln = tiles[tn];
+      nn = tile_nobs(tln.info);
+      if (lane < nn) {
+        mn = meta[tln.obs_begin + lane];
+        if (PREFETCH_J) JStore<S>::load(J, tln.obs_begin + lane, coln);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // 3. the current tile
     S yc[9], yp[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) yc[k] = (S)0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) yp[k] = (S)0;
     if (act) {
-      const int o = tl.obs_begin + lane;
-      const uint32_t m = meta[o];
-      ci = (int)(m & ((1u << kCamBits) - 1));
-      lp = (int)(m >> kCamBits);
-      S col[12][2];
-      JStore<S>::load(J, no_pad, o, col);
-      const S* pc = p + 9 * (size_t)ci;
-      const S* pj = pp_base + 3 * (size_t)(tl.pt_begin + lp);
       S q0 = (S)0, q1 = (S)0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const S v = pc[k];
-        q0 = fma(col[k][0], v, q0);
-        q1 = fma(col[k][1], v, q1);
+        q0 = fma(col[k][0], pcv[k], q0);
+        q1 = fma(col[k][1], pcv[k], q1);
       }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const S v = pj[k];
-        q0 = fma(col[9 + k][0], v, q0);
-        q1 = fma(col[9 + k][1], v, q1);
+        q0 = fma(col[9 + k][0], pjv[k], q0);
+        q1 = fma(col[9 + k][1], pjv[k], q1);
       }
       pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
 #pragma unroll
@@ -90,14 +183,33 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(
         for (int k = 0; k < 9; ++k) atomicAdd(a + k, (double)yc[k]);
       }
     }
-    // cameras outside the LDS set: one row per observation
+    // cameras outside the LDS set: the tile's cold lanes, gathered in camera
+    // order, sum runs of one camera; each run's first lane writes its row
     const bool cold = act && ci >= K;
     const unsigned long long cm = __ballot(cold);
-    if (cold) {
-      const int rank = __popcll(cm & ((1ull << lane) - 1ull));
-      double* row = cold_rows + (size_t)(tl.cold_begin + rank) * 9;
+    if (cm != 0ull) {
+      const int ncold = __popcll(cm);
+      const bool valid = lane < ncold;
+      const int src = valid ? (int)cold_perm[(size_t)t * kWave + lane] : lane;
+      int key = __shfl(ci, src, kWave);
+      key = valid ? key : -1 - lane;
+      double v[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) row[k] = (double)yc[k];
+      for (int k = 0; k < 9; ++k) v[k] = __shfl((double)yc[k], src, kWave);
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int okey = __shfl_down(key, d, kWave);
+        const bool take = (lane + d < kWave) && okey == key;
+        if (!__any(take)) break;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const double o = __shfl_down(v[k], d, kWave);
+          if (take) v[k] += o;
+        }
+      }
+      const int pkey = __shfl_up(key, 1, kWave);
+      const bool head = valid && (lane == 0 || pkey != key);
+      const unsigned long long hm = __ballot(head);
+      if (head) store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, v);
     }
     // points: segmented suffix sums, the first lane of each point holds the total
     const int steps = tile_steps(tl.info);
@@ -121,78 +233,124 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(
         if (tile_first(tl.info)) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            const double v = pp_base[b + k];
+            const double v = pjv[k];
             pap = fma(lambda * (double)dp_base[b + k] * v, v, pap);
           }
         }
       } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const S v = pp_base[b + k];
           const S dv = dp_base[b + k];
-          wp_base[b + k] = fma((S)lambda * dv, v, yp[k]);
-          pap = fma(lambda * (double)dv * (double)v, (double)v, pap);
+          wp_base[b + k] = fma((S)lambda * dv, pjv[k], yp[k]);
+          pap = fma(lambda * (double)dv * (double)pjv[k], (double)pjv[k], pap);
         }
       }
     }
+    // 4. advance
+    tl = tln;
+    n = nn;
+    m = mn;
+    if (PREFETCH_J) {
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        col[j][0] = coln[j][0];
+        col[j][1] = coln[j][1];
+      }
+    } else if (lane < nn) {
+      JStore<S>::load(J, tln.obs_begin + lane, col);
+    }
   }
   // lambda p^T D p of the camera blocks and of points without observations
-  for (int i = blockIdx.x * kMvThreads + tid; i < 9 * nc; i += G * kMvThreads) {
+  for (int i = blockIdx.x * THREADS + tid; i < 9 * nc; i += G * THREADS) {
     const double v = p[i];
     pap = fma(lambda * (double)D[i] * v, v, pap);
   }
-  for (int i = blockIdx.x * kMvThreads + tid; i < 3 * n_orphan; i += G * kMvThreads) {
+  for (int i = blockIdx.x * THREADS + tid; i < 3 * n_orphan; i += G * THREADS) {
     const double v = pp_base[i];
     pap = fma(lambda * (double)dp_base[i] * v, v, pap);
   }
   const double tot = block_sum(pap, red);
   if (tid == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
   double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
-  for (int i = tid; i < K * 9; i += kMvThreads) dst[i] = hot[i];
+  for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
 }
 
 // Camera rows of w, split and orphan points, p^T A p and (in PCG) alpha.
+// Block roles by index:
+//   [0, nb_hot):           column sums of the per-workgroup rows of the LDS
+//                          cameras (64 columns x 4 row groups per block);
+//   [nb_hot, +nb_cold):    one wave per remaining camera, lanes striding its
+//                          observation rows;
+//   the rest:              split points and points without observations.
+// Block 0 also turns the p^T A p partials into pAp (and alpha in PCG).
 template <typename S>
 __global__ __launch_bounds__(256) void k_matvec_final(
-    int nc, int K, int G, const double* __restrict__ hot_rows, const double* __restrict__ cold_rows,
-    const int* __restrict__ cold_off, const int* __restrict__ cold_list, const S* __restrict__ p,
-    const S* __restrict__ D, double lambda, S* __restrict__ w, int n_split,
-    const SplitPoint* __restrict__ sp, const double* __restrict__ split_rows, int n_orphan,
-    const double* __restrict__ partials, DevScalars* __restrict__ sc, int pcg_mode) {
-  __shared__ double red[4];
+    int nc, int K, int G, const double* __restrict__ hot_rows,
+    const double* __restrict__ cold_rows, const int* __restrict__ cold_off,
+    const int* __restrict__ cold_list, const S* __restrict__ p, const S* __restrict__ D, double lambda,
+    S* __restrict__ w, int n_split, const SplitPoint* __restrict__ sp, const double* __restrict__ split_rows,
+    int n_orphan, const double* __restrict__ partials, DevScalars* __restrict__ sc, int pcg_mode, int nb_hot,
+    int nb_cold) {
+  using A = double;
+  __shared__ double red[4][64];
   if (pcg_mode && sc->done) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t ncam = 9 * (int64_t)nc;
-  const int64_t nsplit = 3 * (int64_t)n_split;
-  if (i < ncam) {
-    const int c = (int)(i / 9), k = (int)(i % 9);
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int b = blockIdx.x;
+  if (b < nb_hot) {
+    const int ncol = K * 9;
+    const int col = b * 64 + lane;
     double s = 0.0;
-    if (c < K) {
-      const double* r = hot_rows + (size_t)c * 9 + k;
-      const size_t stride = (size_t)K * 9;
-      for (int g = 0; g < G; ++g) s += r[g * stride];
-    } else {
-      const int b = cold_off[c - K], e = cold_off[c - K + 1];
-      for (int q = b; q < e; ++q) s += cold_rows[(size_t)cold_list[q] * 9 + k];
+    if (col < ncol) {
+      const A* r = hot_rows + col;
+      for (int g = grp; g < G; g += 4) s += (double)r[(size_t)g * ncol];
     }
-    w[i] = (S)fma(lambda * (double)D[i], (double)p[i], s);
-  } else if (i < ncam + nsplit) {
-    const int64_t jx = i - ncam;
-    const SplitPoint s = sp[jx / 3];
-    const int k = (int)(jx % 3);
-    double acc = 0.0;
-    for (int r = 0; r < s.nrows; ++r) acc += split_rows[(size_t)(s.row_begin + r) * kPtRowWidth + k];
-    const size_t b = 9 * (size_t)nc + 3 * (size_t)s.pt + k;
-    w[b] = (S)fma(lambda * (double)D[b], (double)p[b], acc);
-  } else if (i < ncam + nsplit + 3 * (int64_t)n_orphan) {
-    const size_t b = 9 * (size_t)nc + (size_t)(i - ncam - nsplit);
-    w[b] = (S)(lambda * (double)D[b] * (double)p[b]);
+    red[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && col < ncol) {
+      const double tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+      w[col] = (S)fma(lambda * (double)D[col], (double)p[col], tot);
+    }
+  } else if (b < nb_hot + nb_cold) {
+    const int c = K + (b - nb_hot) * 4 + grp;
+    if (c < nc) {
+      const int q0 = cold_off[c - K], q1 = cold_off[c - K + 1];
+      double acc[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+      for (int q = q0 + lane; q < q1; q += 64) {
+        const A* row = cold_rows + (size_t)cold_list[q] * kColdRow;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += (double)row[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double tot = wave_sum(acc[k]);
+        if (lane == 0) {
+          const size_t i = 9 * (size_t)c + k;
+          w[i] = (S)fma(lambda * (double)D[i], (double)p[i], tot);
+        }
+      }
+    }
+  } else {
+    const int64_t i = (int64_t)(b - nb_hot - nb_cold) * 256 + tid;
+    const int64_t nsplit = 3 * (int64_t)n_split;
+    if (i < nsplit) {
+      const SplitPoint s = sp[i / 3];
+      const int k = (int)(i % 3);
+      double acc = 0.0;
+      for (int r = 0; r < s.nrows; ++r) acc += split_rows[(size_t)(s.row_begin + r) * kPtRowWidth + k];
+      const size_t bi = 9 * (size_t)nc + 3 * (size_t)s.pt + k;
+      w[bi] = (S)fma(lambda * (double)D[bi], (double)p[bi], acc);
+    } else if (i < nsplit + 3 * (int64_t)n_orphan) {
+      const size_t bi = 9 * (size_t)nc + (size_t)(i - nsplit);
+      w[bi] = (S)(lambda * (double)D[bi] * (double)p[bi]);
+    }
   }
-  if (blockIdx.x == 0) {
+  if (b == 0) {
     double s = 0.0;
-    for (int g = threadIdx.x; g < G; g += blockDim.x) s += partials[(size_t)g * kPartialWidth];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) {
+    for (int g = tid; g < G; g += blockDim.x) s += partials[(size_t)g * kPartialWidth];
+    s = block_sum(s, &red[0][0]);
+    if (tid == 0) {
       sc->pAp = s;
       if (pcg_mode) {
         sc->iter += 1;
@@ -210,36 +368,79 @@ __global__ __launch_bounds__(256) void k_matvec_final(
 template <typename S>
 static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mode) {
   hipStream_t st = h->stream;
+  constexpr int T = MvCfg<S>::threads;
   const size_t lds = (size_t)h->K * 9 * sizeof(double);
   const DevScalars* scp = pcg_mode ? h->scal : nullptr;
   if (h->n_tiles > 0 || h->nc > 0 || h->n_orphan_pts > 0) {
-    k_matvec<S><<<h->G, kMvThreads, lds, st>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, h->no_pad, p,
-                                                (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts,
-                                                h->hot_rows, h->cold_rows, h->split_rows, h->partials, scp);
+    k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(h->nc, p, (S*)h->p_cam, scp);
     CBA_LAUNCHED();
+    auto kern = k_matvec<S, T, MvCfg<S>::prefetch_j>;
+    if (lds > 65536)
+      CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget));
+    timing_mark_start(h);
+    kern<<<h->G, T, lds, st>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->p_cam, h->cold_perm, p,
+                               (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows,
+                               (double*)h->cold_rows, h->split_rows, h->partials, scp);
+    CBA_LAUNCHED();
+    timing_mark_stop(h);
   }
-  const int64_t n = 9 * (int64_t)h->nc + 3 * (int64_t)h->n_split_pts + 3 * (int64_t)h->n_orphan_pts;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, (n + 255) / 256);
-  k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, h->hot_rows, h->cold_rows, h->cold_off,
-                                          h->cold_list, p, (const S*)h->vec.D, lambda, w, h->n_split_pts,
-                                          h->split_pts, h->split_rows, h->n_orphan_pts, h->partials, h->scal,
-                                          pcg_mode ? 1 : 0);
+  const int nb_hot = (h->K * 9 + 63) / 64;
+  const int nb_cold = (h->nc - h->K + 3) / 4;
+  const int64_t nrest = 3 * (int64_t)h->n_split_pts + 3 * (int64_t)h->n_orphan_pts;
+  const int nb_rest = (int)((nrest + 255) / 256);
+  const unsigned grid = (unsigned)std::max(1, nb_hot + nb_cold + nb_rest);
+  k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, (const double*)h->hot_rows,
+                                          (const double*)h->cold_rows, h->cold_off, h->cold_list, p,
+                                          (const S*)h->vec.D, lambda, w, h->n_split_pts, h->split_pts,
+                                          h->split_rows, h->n_orphan_pts, h->partials, h->scal, pcg_mode ? 1 : 0,
+                                          nb_hot, nb_cold);
   CBA_LAUNCHED();
 }
 
-void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode) {
-  const int lds = h->K * 9 * (int)sizeof(double);
-  if (h->prec == CASPAR_FP64) {
-    if (lds > 65536)
-      CBA_HIP(hipFuncSetAttribute((const void*)k_matvec<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kLdsBudget));
-    matvec_t<double>(h, lambda, (const double*)p, (double*)w, pcg_mode);
-  } else {
-    if (lds > 65536)
-      CBA_HIP(hipFuncSetAttribute((const void*)k_matvec<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kLdsBudget));
-    matvec_t<float>(h, lambda, (const float*)p, (float*)w, pcg_mode);
+// Bytes the fused product must move per launch: the Jacobian blocks and the
+// meta word of every observation, and p read, D read, w written once per
+// parameter.
+double matvec_algorithmic_bytes(const caspar_ba* h) {
+  const double s = (double)scalar_bytes(h->prec);
+  return (double)h->no * (24.0 * s + 4.0) + 3.0 * s * (double)h->N;
+}
+
+void timing_mark_start(caspar_ba* h) {
+  if (!h->timing) return;
+  if (h->ev_used == (int)h->ev_start.size()) {
+    hipEvent_t a, b;
+    CBA_HIP(hipEventCreate(&a));
+    CBA_HIP(hipEventCreate(&b));
+    h->ev_start.push_back(a);
+    h->ev_stop.push_back(b);
   }
+  CBA_HIP(hipEventRecord(h->ev_start[h->ev_used], h->stream));
+}
+
+void timing_mark_stop(caspar_ba* h) {
+  if (!h->timing) return;
+  CBA_HIP(hipEventRecord(h->ev_stop[h->ev_used], h->stream));
+  ++h->ev_used;
+}
+
+void timing_harvest(caspar_ba* h, int effective) {
+  if (!h->timing) return;
+  const int n = std::min(effective, h->ev_used);
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.f;
+    CBA_HIP(hipEventSynchronize(h->ev_stop[i]));
+    CBA_HIP(hipEventElapsedTime(&ms, h->ev_start[i], h->ev_stop[i]));
+    h->mv_ms += ms;
+  }
+  h->mv_launches += n;
+  h->ev_used = 0;
+}
+
+void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode) {
+  if (h->prec == CASPAR_FP64)
+    matvec_t<double>(h, lambda, (const double*)p, (double*)w, pcg_mode);
+  else
+    matvec_t<float>(h, lambda, (const float*)p, (float*)w, pcg_mode);
 }
 
 }  // namespace cba

@@ -223,9 +223,19 @@ __device__ inline void so3_grad_to_tangent(const double w[3], const double g[3],
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 
-// Jacobian storage: blocked structure-of-arrays of 16-byte chunks, chunk-major
-// ([chunk][observation]), so a wave's 64 lanes read 1 KiB contiguous per
-// chunk.
+// Jacobian storage: blocked structure-of-arrays.  Observations are grouped
+// in blocks of kJBlock; inside a block each 16-byte chunk (two Jacobian
+// columns x two rows in float64, four columns in float32) is stored for all
+// kJBlock observations before the next chunk:
+//   chunk k of observation o lives at ((o / kJBlock) * kChunks + k) * kJBlock + o % kJBlock
+// so a wave's 64 lanes read 1 KiB contiguous per chunk and a workgroup's
+// consecutive tiles stream one contiguous region.
+constexpr int kJBlock = 1024;
+
+__device__ __host__ inline size_t jidx(int o, int k, int nchunks) {
+  return ((size_t)(o / kJBlock) * nchunks + k) * kJBlock + (o % kJBlock);
+}
+
 template <typename S>
 struct JStore;
 
@@ -233,16 +243,16 @@ struct JStore;
 template <>
 struct JStore<double> {
   static constexpr int kChunks = 12;
-  __device__ static void store(void* J, int no_pad, int o, const double col[12][2]) {
+  __device__ static void store(void* J, int o, const double col[12][2]) {
     double2* Jv = reinterpret_cast<double2*>(J);
 #pragma unroll
-    for (int j = 0; j < 12; ++j) Jv[(size_t)j * no_pad + o] = make_double2(col[j][0], col[j][1]);
+    for (int j = 0; j < 12; ++j) Jv[jidx(o, j, kChunks)] = make_double2(col[j][0], col[j][1]);
   }
-  __device__ static void load(const void* J, int no_pad, int o, double col[12][2]) {
+  __device__ static void load(const void* J, int o, double col[12][2]) {
     const dvec2* Jv = reinterpret_cast<const dvec2*>(J);
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
-      const dvec2 v = __builtin_nontemporal_load(&Jv[(size_t)j * no_pad + o]);
+      const dvec2 v = __builtin_nontemporal_load(&Jv[jidx(o, j, kChunks)]);
       col[j][0] = v.x;
       col[j][1] = v.y;
     }
@@ -253,17 +263,17 @@ struct JStore<double> {
 template <>
 struct JStore<float> {
   static constexpr int kChunks = 6;
-  __device__ static void store(void* J, int no_pad, int o, const float col[12][2]) {
+  __device__ static void store(void* J, int o, const float col[12][2]) {
     float4* Jv = reinterpret_cast<float4*>(J);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      Jv[(size_t)k * no_pad + o] = make_float4(col[2 * k][0], col[2 * k][1], col[2 * k + 1][0], col[2 * k + 1][1]);
+      Jv[jidx(o, k, kChunks)] = make_float4(col[2 * k][0], col[2 * k][1], col[2 * k + 1][0], col[2 * k + 1][1]);
   }
-  __device__ static void load(const void* J, int no_pad, int o, float col[12][2]) {
+  __device__ static void load(const void* J, int o, float col[12][2]) {
     const fvec4* Jv = reinterpret_cast<const fvec4*>(J);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const fvec4 v = __builtin_nontemporal_load(&Jv[(size_t)k * no_pad + o]);
+      const fvec4 v = __builtin_nontemporal_load(&Jv[jidx(o, k, kChunks)]);
       col[2 * k][0] = v.x;
       col[2 * k][1] = v.y;
       col[2 * k + 1][0] = v.z;

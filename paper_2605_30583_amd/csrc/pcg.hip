@@ -417,6 +417,7 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
     launched += check_every;
     s = read_scalars(h);
   }
+  timing_harvest(h, s.iter);
   if (!s.done) fail(CASPAR_ENUMERIC, "internal: PCG did not reach its stop condition");
   if (rel_resid) *rel_resid = s.bb > 0.0 ? std::sqrt(std::max(s.rr, 0.0) / s.bb) : 0.0;
   return s.iter;

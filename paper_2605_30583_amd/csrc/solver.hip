@@ -52,7 +52,7 @@ __global__ void k_adjoint_rhs(int nc, int np, const double* __restrict__ cam, co
 // dL/dpx_o = J_o v in caller order.
 template <typename S>
 __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-                              const void* __restrict__ J, int no_pad, const S* __restrict__ v, int nc,
+                              const void* __restrict__ J, const S* __restrict__ v, int nc,
                               const int* __restrict__ s2c, double* __restrict__ out) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -64,7 +64,7 @@ __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const
   const int ci = (int)(m & ((1u << kCamBits) - 1));
   const int pi = tl.pt_begin + (int)(m >> kCamBits);
   S col[12][2];
-  JStore<S>::load(J, no_pad, o, col);
+  JStore<S>::load(J, o, col);
   double q0 = 0.0, q1 = 0.0;
   for (int k = 0; k < 9; ++k) {
     const double x = v[9 * (size_t)ci + k];
@@ -186,7 +186,7 @@ template <typename S>
 static void adjoint_obs_t(caspar_ba* h, double* out) {
   if (h->n_tiles == 0) return;
   k_adjoint_obs<S><<<nblk((int64_t)h->n_tiles * kWave, 256), 256, 0, h->stream>>>(
-      h->n_tiles, h->tiles, h->meta, h->J, h->no_pad, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+      h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
   CBA_LAUNCHED();
 }
 
@@ -245,6 +245,7 @@ int caspar_ba_matvec(caspar_ba* h, double lambda, const double* p, double* w, do
   run_matvec(h, lambda, h->vec.v, h->vec.w, false);
   run_to_caller_vector(h, h->vec.w, w);
   const DevScalars s = read_scalars(h);
+  timing_harvest(h, 1);
   if (pAp) *pAp = s.pAp;
   CBA_API_END
 }
@@ -287,6 +288,27 @@ int caspar_ba_cost_fp64(caspar_ba* h, double* cost) {
   CBA_REQUIRE(h != nullptr && cost != nullptr, "NULL argument");
   check_device(h);
   *cost = run_cost(h, h->cam, h->X, true);
+  CBA_API_END
+}
+
+int caspar_ba_set_timing(caspar_ba* h, int enable) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  h->timing = enable != 0;
+  h->ev_used = 0;
+  if (h->timing) {
+    h->mv_launches = 0;
+    h->mv_ms = 0.0;
+  }
+  CBA_API_END
+}
+
+int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr && out != nullptr, "NULL argument");
+  out->matvec_launches = h->mv_launches;
+  out->matvec_ms = h->mv_ms;
+  out->matvec_bytes = matvec_algorithmic_bytes(h);
   CBA_API_END
 }
 

@@ -1,0 +1,78 @@
+"""The large Zipf-skewed workload (13,700 cameras, 4.4M points, ~29M
+observations) in the configuration the benchmark times, checked against the
+oracle on quantities it can compute: the total cost over every observation,
+and the gradient and the fused product at sampled points and cameras
+(including the most observed camera and cameras outside the LDS set).  For a
+sampled column, the oracle's sparse J restricted to the rows of the
+observations that touch it gives the exact full-size value."""
+import numpy as np
+import pytest
+
+from oracle import camera, linear
+from synth import scene_config
+
+from gpu_helpers import handle_for, rel, t64
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def large():
+    sc = scene_config("large_zipf")
+    st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
+    px = np.empty((sc.n_obs, 2))
+    step = 4_000_000
+    for b in range(0, sc.n_obs, step):      # bounded host memory
+        px[b:b + step] = camera.project(st_true, sc.obs_cam[b:b + step], sc.obs_pt[b:b + step])
+    px += sc.noise
+    st0 = camera.State.from_bal(sc.cams_init, sc.points_init)
+    cost = 0.0
+    for b in range(0, sc.n_obs, step):
+        r = camera.residuals(st0, sc.obs_cam[b:b + step], sc.obs_pt[b:b + step], px[b:b + step])
+        cost += 0.5 * float(np.sum(r * r))
+    counts = np.bincount(sc.obs_cam, minlength=sc.n_cams)
+    order = np.argsort(-counts, kind="stable")
+    rng = np.random.default_rng(2024)
+    cams = np.unique(np.concatenate([order[:2], order[[2047, 2048, 5000, -1]], rng.choice(sc.n_cams, 3)]))
+    pts = np.unique(rng.choice(sc.n_points, 40, replace=False))
+    return sc, px, st0, cost, cams, pts
+
+
+def _subset_reference(sc, px, st0, cams, pts, lam, p):
+    rows = np.isin(sc.obs_cam, cams) | np.isin(sc.obs_pt, pts)
+    oc, op = sc.obs_cam[rows], sc.obs_pt[rows]
+    r, Jc, Jp = camera.linearize(st0, oc, op, px[rows])
+    J = linear.jacobian_csr(Jc, Jp, oc, op, sc.n_cams, sc.n_points)
+    D = linear.damping_diagonal(J)
+    g = linear.gradient(J, r.ravel())
+    w = linear.matvec(J, D, lam, p)
+    cols = np.concatenate([(9 * cams[:, None] + np.arange(9)).ravel(),
+                           (9 * sc.n_cams + 3 * pts[:, None] + np.arange(3)).ravel()])
+    return cols, g[cols], D[cols], w[cols]
+
+
+# float64: the longest sums here are the most observed camera's ~2.9M terms;
+# two orders of summing n terms differ by at most about n u = 3.3e-10
+# (u = 2^-53) relative to the sum of magnitudes, so the gate is 1e-10 (the
+# 1e-12 gate applies where the oracle takes the whole problem, at the small
+# sizes).  float32-mixed: products and sums in float32.
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-5)])
+def test_large_workload_cost_gradient_and_product(large, precision, tol):
+    sc, px, st0, cost, cams, pts = large
+    ba = handle_for(sc, px, precision)
+    info = ba.layout_info()
+    assert info["hot_cams"] == 2048
+    assert info["cold_obs"] > 0 and info["matvec_groups"] == 256
+    lin = ba.linearize()
+    assert abs(lin["cost"] - cost) <= tol * cost
+    p = np.random.default_rng(1).normal(size=9 * sc.n_cams + 3 * sc.n_points)
+    lam = 1e-2
+    w, _ = ba.matvec(lam, t64(p))
+    cols, g_ref, d_ref, w_ref = _subset_reference(sc, px, st0, cams, pts, lam, p)
+    g = lin["grad"].cpu().numpy()[cols]
+    d = lin["diag"].cpu().numpy()[cols]
+    w = w.cpu().numpy()[cols]
+    assert rel(g, g_ref) <= tol
+    assert rel(d, d_ref) <= tol
+    assert rel(w, w_ref) <= tol
+    ba.close()

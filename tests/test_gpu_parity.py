@@ -133,14 +133,15 @@ def test_create_rejects_bad_inputs():
         handle_for(sc, pxn)
 
 
-def test_cold_camera_rows_and_full_lds():
+@pytest.mark.parametrize("zipf", [None, 0.9])
+def test_cold_camera_rows_and_full_lds(zipf):
     # more cameras than the LDS holds: the least observed ones go through rows
     from synth import make_scene
-    sc = make_scene(2300, 6000, 17, k_values=(2, 3, 4), k_probs=(0.3, 0.4, 0.3))
+    sc = make_scene(2300, 6000, 17, k_values=(2, 3, 4), k_probs=(0.3, 0.4, 0.3), zipf_s=zipf)
     px = observed_pixels(sc)
     ba = handle_for(sc, px)
     info = ba.layout_info()
-    assert info["hot_cams"] == 2048 and info["cold_obs"] > 0
+    assert info["hot_cams"] == 2048 and info["cold_obs"] > 0      # float64: 2048 cameras in LDS
     ref = oracle_lin(sc, px)
     out = ba.linearize()
     assert rel(out["grad"].cpu(), ref.g) <= 1e-12
@@ -151,3 +152,24 @@ def test_cold_camera_rows_and_full_lds():
         w_ref = linear.matvec(ref.J, ref.D, lam, p)
         assert rel(w.cpu(), w_ref) <= 1e-12
         assert abs(pap - p @ w_ref) <= 1e-12 * abs(p @ w_ref)
+
+
+def test_mixed_precision_cold_rows_and_products():
+    # float32-mixed with cameras outside the LDS set; Zipf-skewed visibility
+    # with points grouped by their least observed camera, so several
+    # observations of one cold camera share a tile and a row
+    from synth import make_scene
+    sc = make_scene(5000, 20000, 19, k_values=(3, 4), k_probs=(0.5, 0.5), zipf_s=0.8)
+    px = observed_pixels(sc)
+    ba = handle_for(sc, px, precision=1)
+    info = ba.layout_info()
+    assert info["hot_cams"] == 2048 and info["cold_obs"] > 0
+    ref = oracle_lin(sc, px)
+    lin = ba.linearize()
+    assert abs(lin["cost"] - ref.cost) <= 1e-6 * ref.cost
+    assert rel(lin["jac_cam"].cpu(), ref.Jc) <= 1e-5
+    p = np.random.default_rng(9).normal(size=9 * sc.n_cams + 3 * sc.n_points)
+    w, pap = ba.matvec(1e-2, t64(p))
+    w_ref = linear.matvec(ref.J, ref.D, 1e-2, p)
+    assert rel(w.cpu(), w_ref) <= 2e-5
+    assert abs(pap - p @ w_ref) <= 2e-5 * abs(p @ w_ref)
