@@ -149,9 +149,15 @@ CASPAR_API int caspar_ba_set_observations(caspar_ba* h, const double* obs_px);
  * translation, f, k1, k2; may be NULL = 0) is mapped to the right tangent
  * with the inverse right Jacobian of SO(3); grad_points (dev [n_points][3],
  * may be NULL = 0).  J and D are those of the current parameters.
- * pcg_iters (host, may be NULL) receives the iteration count. */
+ * flags: CASPAR_ADJ_GAUGE_PROJECT removes the D-weighted component of g
+ * along the 7 similarity-gauge directions N (world rotation, translation,
+ * scale): g <- g - D N (N^T D N)^-1 N^T g.  Because J N = 0 and
+ * A N = lambda_adj D N this leaves J A^-1 g unchanged, and it keeps v free
+ * of the 1/lambda_adj gauge component, so small lambda_adj stay well
+ * conditioned.  pcg_iters (host, may be NULL) receives the iteration count. */
+enum { CASPAR_ADJ_GAUGE_PROJECT = 1 };
 CASPAR_API int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points,
-                       double lambda_adj, double pcg_tol, int32_t max_pcg_iters,
+                       double lambda_adj, double pcg_tol, int32_t max_pcg_iters, int32_t flags,
                        double* grad_obs_px, int32_t* pcg_iters);
 
 /* ---- Parity hooks: single steps of the hot path at the current parameters ---- */

@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcaspar_b
 
 FP64 = 0
 FP32_MIXED = 1
+ADJ_GAUGE_PROJECT = 1
 STATUS = {0: "CASPAR_OK", -1: "CASPAR_EINVAL", -2: "CASPAR_EHIP", -3: "CASPAR_ENOMEM", -4: "CASPAR_ENUMERIC"}
 
 
@@ -46,7 +47,7 @@ SIGNATURES = [
     ("caspar_ba_get_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_observations", C.c_int, [_P, _P]),
-    ("caspar_ba_backward", C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, _P,
+    ("caspar_ba_backward", C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, _P,
                                      C.POINTER(C.c_int32)]),
     ("caspar_ba_linearize", C.c_int, [_P, _D, _P, _P, _P, _P, _P]),
     ("caspar_ba_matvec", C.c_int, [_P, C.c_double, _P, _P, _D]),

@@ -181,15 +181,17 @@ class BundleAdjuster:
         check(self._lib.caspar_ba_cost_fp64(self._h, C.byref(c)))
         return c.value
 
-    def backward(self, grad_cams=None, grad_points=None, lambda_adj=1e-4, pcg_tol=1e-10, max_pcg_iters=2000):
+    def backward(self, grad_cams=None, grad_points=None, lambda_adj=1e-4, pcg_tol=1e-10, max_pcg_iters=2000,
+                 gauge_project=False):
         if grad_cams is not None:
             _dev(grad_cams, torch.float64, (self.n_cams, 9), "grad_cams")
         if grad_points is not None:
             _dev(grad_points, torch.float64, (self.n_points, 3), "grad_points")
         out = torch.empty((self.n_obs, 2), dtype=torch.float64, device=self.device)
         it = C.c_int32()
+        flags = _native.ADJ_GAUGE_PROJECT if gauge_project else 0
         check(self._lib.caspar_ba_backward(self._h, _ptr(grad_cams), _ptr(grad_points), float(lambda_adj),
-                                           float(pcg_tol), int(max_pcg_iters), _ptr(out), C.byref(it)))
+                                           float(pcg_tol), int(max_pcg_iters), flags, _ptr(out), C.byref(it)))
         self.last_backward_iters = it.value
         return out
 

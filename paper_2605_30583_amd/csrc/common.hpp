@@ -192,6 +192,7 @@ struct caspar_ba {
   cba::Vectors vec;
 
   double* partials = nullptr;   // [kMaxPartials][4]
+  double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
   cba::DevScalars* scal = nullptr;
 
   // kernel timing (roofline reporting)
@@ -218,7 +219,7 @@ struct Plan {
   };
   Region cam, cam_trial, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_perm, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
-      split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal;
+      split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;

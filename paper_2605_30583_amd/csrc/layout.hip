@@ -89,6 +89,7 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
   };
   take(p.scal, sizeof(DevScalars));
   take(p.partials, (size_t)kMaxPartials * kPartialWidth * 8);
+  take(p.gauge_rows, 256 * 35 * 8);
   take(p.cam, (size_t)nc * kCamStride * 8);
   take(p.cam_trial, (size_t)nc * kCamStride * 8);
   take(p.X, (size_t)np * 3 * 8);
@@ -638,6 +639,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     char* ws = (char*)workspace;
     h->scal = (DevScalars*)(ws + plan.scal.off);
     h->partials = (double*)(ws + plan.partials.off);
+    h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
     h->cam = (double*)(ws + plan.cam.off);
     h->cam_trial = (double*)(ws + plan.cam_trial.off);
     h->X = (double*)(ws + plan.X.off);

@@ -49,6 +49,81 @@ __global__ void k_adjoint_rhs(int nc, int np, const double* __restrict__ cam, co
   }
 }
 
+// Gauge directions at the current parameters, right-perturbation tangent:
+//   rotation about e_k:    dw = -e_k,            dX = e_k x X
+//   translation along e_k: dt = -R e_k,          dX = e_k
+//   scale:                 dt = t,               dX = X
+// n[a][i] for the block's components (9 for a camera, 3 for a point).
+__device__ inline void gauge_block(bool cam, const double* row_or_X, double n[7][9]) {
+  for (int a = 0; a < 7; ++a)
+    for (int i = 0; i < 9; ++i) n[a][i] = 0.0;
+  if (cam) {
+    const double* R = row_or_X;
+    const double* t = row_or_X + 9;
+    for (int k = 0; k < 3; ++k) {
+      n[k][k] = -1.0;
+      for (int j = 0; j < 3; ++j) n[3 + k][3 + j] = -R[3 * j + k];
+    }
+    for (int j = 0; j < 3; ++j) n[6][3 + j] = t[j];
+  } else {
+    const double* X = row_or_X;
+    n[0][0] = 0.0;  n[0][1] = -X[2]; n[0][2] = X[1];   // e_0 x X
+    n[1][0] = X[2]; n[1][1] = 0.0;   n[1][2] = -X[0];  // e_1 x X
+    n[2][0] = -X[1]; n[2][1] = X[0]; n[2][2] = 0.0;    // e_2 x X
+    for (int k = 0; k < 3; ++k) n[3 + k][k] = 1.0;
+    for (int j = 0; j < 3; ++j) n[6][j] = X[j];
+  }
+}
+
+constexpr int kGaugeStats = 35;  // 28 entries of N^T D N (upper) + 7 of N^T g
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_gauge_stats(int nc, int np, const double* __restrict__ cam,
+                                                     const double* __restrict__ X, const S* __restrict__ D,
+                                                     const S* __restrict__ g, double* __restrict__ rows) {
+  __shared__ double red[4];
+  double acc[kGaugeStats];
+  for (int k = 0; k < kGaugeStats; ++k) acc[k] = 0.0;
+  const int64_t nb = (int64_t)nc + np;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const bool is_cam = b < nc;
+    double n[7][9];
+    gauge_block(is_cam, is_cam ? cam + (size_t)b * kCamStride : X + 3 * (size_t)(b - nc), n);
+    const int len = is_cam ? 9 : 3;
+    const size_t o = is_cam ? 9 * (size_t)b : 9 * (size_t)nc + 3 * (size_t)(b - nc);
+    for (int i = 0; i < len; ++i) {
+      const double d = (double)D[o + i], gi = (double)g[o + i];
+      int q = 0;
+      for (int a2 = 0; a2 < 7; ++a2)
+        for (int c2 = a2; c2 < 7; ++c2) acc[q++] += n[a2][i] * d * n[c2][i];
+      for (int a2 = 0; a2 < 7; ++a2) acc[28 + a2] += n[a2][i] * gi;
+    }
+  }
+  for (int k = 0; k < kGaugeStats; ++k) {
+    const double s = block_sum(acc[k], red);
+    if (threadIdx.x == 0) rows[(size_t)blockIdx.x * kGaugeStats + k] = s;
+  }
+}
+
+template <typename S>
+__global__ void k_gauge_apply(int nc, int np, const double* __restrict__ cam, const double* __restrict__ X,
+                              const S* __restrict__ D, S* __restrict__ g, double c0, double c1, double c2, double c3,
+                              double c4, double c5, double c6) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= (int64_t)nc + np) return;
+  const double c[7] = {c0, c1, c2, c3, c4, c5, c6};
+  const bool is_cam = b < nc;
+  double n[7][9];
+  gauge_block(is_cam, is_cam ? cam + (size_t)b * kCamStride : X + 3 * (size_t)(b - nc), n);
+  const int len = is_cam ? 9 : 3;
+  const size_t o = is_cam ? 9 * (size_t)b : 9 * (size_t)nc + 3 * (size_t)(b - nc);
+  for (int i = 0; i < len; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < 7; ++a) s += n[a][i] * c[a];
+    g[o + i] = (S)((double)g[o + i] - (double)D[o + i] * s);
+  }
+}
+
 // dL/dpx_o = J_o v in caller order.
 template <typename S>
 __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
@@ -190,6 +265,66 @@ static void adjoint_obs_t(caspar_ba* h, double* out) {
   CBA_LAUNCHED();
 }
 
+// g <- g - D N (N^T D N)^-1 N^T g on the handle's vector v.
+template <typename S>
+static void gauge_project_t(caspar_ba* h) {
+  const int64_t nb = (int64_t)h->nc + h->np;
+  if (nb == 0) return;
+  const int grid = (int)std::min<int64_t>(256, (nb + 255) / 256);
+  k_gauge_stats<S><<<grid, 256, 0, h->stream>>>(h->nc, h->np, h->cam, h->X, (const S*)h->vec.D,
+                                                 (const S*)h->vec.v, h->gauge_rows);
+  CBA_LAUNCHED();
+  std::vector<double> rows((size_t)grid * kGaugeStats);
+  CBA_HIP(hipMemcpyAsync(rows.data(), h->gauge_rows, rows.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+  double M[7][7], r[7];
+  for (int a = 0; a < 7; ++a) r[a] = 0.0;
+  for (int a = 0; a < 7; ++a)
+    for (int b = 0; b < 7; ++b) M[a][b] = 0.0;
+  for (int k = 0; k < grid; ++k) {
+    int q = 0;
+    for (int a = 0; a < 7; ++a)
+      for (int b = a; b < 7; ++b) M[a][b] += rows[(size_t)k * kGaugeStats + q++];
+    for (int a = 0; a < 7; ++a) r[a] += rows[(size_t)k * kGaugeStats + 28 + a];
+  }
+  for (int a = 0; a < 7; ++a)
+    for (int b = 0; b < a; ++b) M[a][b] = M[b][a];
+  // Gaussian elimination with partial pivoting on the 7x7 system M c = r
+  int piv[7];
+  for (int i = 0; i < 7; ++i) piv[i] = i;
+  double c[7] = {0, 0, 0, 0, 0, 0, 0};
+  double scale = 0.0;
+  for (int a = 0; a < 7; ++a) scale = std::max(scale, std::fabs(M[a][a]));
+  bool ok = scale > 0.0;
+  for (int col = 0; col < 7 && ok; ++col) {
+    int best = col;
+    for (int i = col + 1; i < 7; ++i)
+      if (std::fabs(M[i][col]) > std::fabs(M[best][col])) best = i;
+    if (std::fabs(M[best][col]) <= 1e-13 * scale) {
+      ok = false;
+      break;
+    }
+    if (best != col) {
+      for (int j = 0; j < 7; ++j) std::swap(M[col][j], M[best][j]);
+      std::swap(r[col], r[best]);
+    }
+    for (int i = col + 1; i < 7; ++i) {
+      const double f = M[i][col] / M[col][col];
+      for (int j = col; j < 7; ++j) M[i][j] -= f * M[col][j];
+      r[i] -= f * r[col];
+    }
+  }
+  if (!ok) fail(CASPAR_ENUMERIC, "gauge projection: N^T D N is singular (degenerate problem)");
+  for (int i = 6; i >= 0; --i) {
+    double s = r[i];
+    for (int j = i + 1; j < 7; ++j) s -= M[i][j] * c[j];
+    c[i] = s / M[i][i];
+  }
+  k_gauge_apply<S><<<nblk(nb, 256), 256, 0, h->stream>>>(h->nc, h->np, h->cam, h->X, (const S*)h->vec.D,
+                                                          (S*)h->vec.v, c[0], c[1], c[2], c[3], c[4], c[5], c[6]);
+  CBA_LAUNCHED();
+}
+
 }  // namespace cba
 
 using namespace cba;
@@ -313,7 +448,8 @@ int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out) {
 }
 
 int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points, double lambda_adj,
-                       double pcg_tol, int32_t max_pcg_iters, double* grad_obs_px, int32_t* pcg_iters) {
+                       double pcg_tol, int32_t max_pcg_iters, int32_t flags, double* grad_obs_px,
+                       int32_t* pcg_iters) {
   CBA_API_BEGIN
   CBA_REQUIRE(h != nullptr, "handle is NULL");
   CBA_REQUIRE(h->no == 0 || grad_obs_px != nullptr, "grad_obs_px is NULL");
@@ -321,10 +457,17 @@ int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad
   CBA_REQUIRE(pcg_tol >= 0.0 && max_pcg_iters >= 0, "bad PCG arguments");
   check_device(h);
   ensure_linearized(h);
+  CBA_REQUIRE((flags & ~CASPAR_ADJ_GAUGE_PROJECT) == 0, "unknown backward flags");
   if (h->prec == CASPAR_FP64)
     adjoint_rhs_t<double>(h, grad_cams, grad_points);
   else
     adjoint_rhs_t<float>(h, grad_cams, grad_points);
+  if (flags & CASPAR_ADJ_GAUGE_PROJECT) {
+    if (h->prec == CASPAR_FP64)
+      gauge_project_t<double>(h);
+    else
+      gauge_project_t<float>(h);
+  }
   double rel = 0.0;
   const int k = run_pcg(h, lambda_adj, h->vec.v, false, pcg_tol, max_pcg_iters, 4, nullptr, &rel);
   if (h->prec == CASPAR_FP64)

@@ -2,7 +2,9 @@
 results on the tiny and medium synthetic workloads.
 
 Calls only synth/ and oracle/ (exact Schur-complement steps, float64).
-Run from the repository root:  python tests/golden/make_golden.py
+Run from the repository root:
+    python tests/golden/make_golden.py [workload ...]
+(default: all; named workloads are recomputed and merged into the file).
 """
 import json
 import os
@@ -17,14 +19,19 @@ sys.path.insert(0, ROOT)
 from oracle import camera, lm  # noqa: E402
 from synth import scene_config  # noqa: E402
 
-RUNS = {"tiny": 20, "medium": 30}
+RUNS = {"tiny": 20, "medium": 30, "bal1700": 20}
 
 
 def main():
+    path = os.path.join(ROOT, "tests", "golden", "lm_reference.json")
     out = {"source": "oracle.lm.solve with exact Schur-complement steps (float64); lambda0 1e-2; "
                      "observed pixels = oracle.camera.project(true parameters) + the scene's noise",
            "runs": {}}
-    for name, iters in RUNS.items():
+    if os.path.exists(path):
+        out["runs"] = json.load(open(path))["runs"]
+    names = sys.argv[1:] or list(RUNS)
+    for name in names:
+        iters = RUNS[name]
         sc = scene_config(name)
         st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
         px = camera.project(st_true, sc.obs_cam, sc.obs_pt) + sc.noise
@@ -43,7 +50,6 @@ def main():
             "oracle_seconds": time.time() - t,
         }
         print(name, res.initial_cost, res.final_cost, f"{time.time() - t:.1f}s", flush=True)
-    path = os.path.join(ROOT, "tests", "golden", "lm_reference.json")
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 
