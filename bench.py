@@ -42,6 +42,10 @@ def parse():
                     choices=["tiny", "medium", "bal1700", "large_zipf"])
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     ap.add_argument("--pcg-tol", type=float, default=1e-3, help="PCG relative tolerance (paper: 1e-3)")
+    ap.add_argument("--jacobian", default="stored", choices=["stored", "recompute"],
+                    help="store the Jacobian blocks at linearisation or evaluate them in every product")
+    ap.add_argument("--no-alt-jacobian", action="store_true",
+                    help="skip the run with the other Jacobian handling beside the headline one")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 plain solve beside the mixed one")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -62,10 +66,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload: str, precision: str):
+def counter_traffic(workload: str, precision: str, jacobian: str):
     """HBM bytes per fused-product launch from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(PROFILES, f"matvec_{workload}_{precision}_counters.json")
+    path = os.path.join(PROFILES, f"matvec_{workload}_{precision}_{jacobian}_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -140,9 +144,9 @@ def main():
     cams0, pts0 = t64(sc.cams_init), t64(sc.points_init)
     prec = FP32_MIXED if a.precision == "fp32_mixed" else FP64
 
-    def timed_solve(precision, label):
+    def timed_solve(precision, label, jacobian=a.jacobian):
         t = time.time()
-        ba = BundleAdjuster(cams0, pts0, oc, op, px, precision)
+        ba = BundleAdjuster(cams0, pts0, oc, op, px, precision, recompute_jacobian=(jacobian == "recompute"))
         torch.cuda.synchronize()
         log(f"{label}: create {time.time() - t:.2f}s, layout {ba.layout_info()}")
         if a.warmup > 0:
@@ -184,6 +188,21 @@ def main():
         del ba64
         torch.cuda.empty_cache()
 
+    if not a.no_alt_jacobian:
+        alt = "recompute" if a.jacobian == "stored" else "stored"
+        ba_alt, st_alt, dt_alt, tim_alt = timed_solve(prec, f"{a.precision}/{alt}", jacobian=alt)
+        mv_alt = tim_alt["matvec_ms"] / max(1, tim_alt["matvec_launches"])
+        extra[f"{alt}_jacobian"] = {
+            "lm_iters_per_s": st_alt["lm_iters"] / dt_alt,
+            "ms_per_step": 1e3 * dt_alt / max(1, st_alt["lm_iters"]),
+            "final_cost_fp64_eval": ba_alt.cost_fp64(),
+            "pcg_iters_total": st_alt["pcg_iters_total"],
+            "matvec_avg_ms": mv_alt,
+            "matvec_algorithmic_bytes": tim_alt["matvec_bytes"],
+        }
+        del ba_alt
+        torch.cuda.empty_cache()
+
     if not a.no_adjoint:
         _, pts = ba.get_params()
         torch.cuda.synchronize()
@@ -209,7 +228,7 @@ def main():
         "config": {
             "workload": a.workload,
             "n_cams": sc.n_cams, "n_points": sc.n_points, "n_obs": sc.n_obs,
-            "precision": a.precision, "pcg_tol": a.pcg_tol,
+            "precision": a.precision, "jacobian": a.jacobian, "pcg_tol": a.pcg_tol,
             "pcg_iters_per_lm_iter": st["pcg_iters_total"] / max(1, iters),
             "accepted": st["accepted"],
             "final_cost_fp64_eval": f_primary,
@@ -221,7 +240,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": counter_traffic(a.workload, a.precision),
+            "traffic": counter_traffic(a.workload, a.precision, a.jacobian),
             "kernel": "k_matvec",
             "avg_ms": mv_avg_ms,
             "launches": tim["matvec_launches"],

@@ -56,6 +56,17 @@ typedef struct caspar_ba caspar_ba; /* opaque handle */
  *   inversion, and the parameters themselves. */
 enum { CASPAR_FP64 = 0, CASPAR_FP32_MIXED = 1 };
 
+/* Jacobian handling, OR-ed into the mode argument of create and
+ * workspace_bytes.  By default the linearisation stores the 2x9 / 2x3 blocks
+ * of every observation and each normal-equation product streams them from
+ * HBM.  With CASPAR_RECOMPUTE_JACOBIAN nothing per observation is stored
+ * beyond its indices: every product (and the adjoint) evaluates the blocks
+ * again from the camera row and the point coordinates, trading about 70
+ * arithmetic operations per observation for 96 (float32) or 192 (float64)
+ * bytes of HBM traffic.  Results are identical up to rounding order; the
+ * blocks are bitwise the same as the stored ones. */
+enum { CASPAR_RECOMPUTE_JACOBIAN = 0x10 };
+
 enum {
   CASPAR_OK = 0,
   CASPAR_EINVAL = -1,   /* bad argument, index out of range, non-finite input */
@@ -106,10 +117,11 @@ typedef struct caspar_iter_record {
 CASPAR_API void caspar_default_solve_opts(caspar_solve_opts* opts);
 
 /* Bytes of device workspace a handle of this size needs (0 on bad sizes).
- * n_obs must be < 2^31, n_cams < 2^25. */
-CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int precision);
+ * n_obs must be < 2^31, n_cams < 2^25.  mode = precision | Jacobian flag. */
+CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int mode);
 
 /* Build a problem (paper Sec. VI-A: cameras, points, observations).
+ * mode = CASPAR_FP64 or CASPAR_FP32_MIXED, optionally | CASPAR_RECOMPUTE_JACOBIAN.
  * cams (dev) [n_cams][9] BAL; points (dev) [n_points][3]; obs_cam, obs_pt
  * (dev) int32 [n_obs]; obs_px (dev) [n_obs][2].  workspace (dev, >= 256-byte
  * aligned, caspar_ba_workspace_bytes() long) must outlive the handle; the
@@ -119,7 +131,7 @@ CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, in
  * camera); that order never shows at the boundary. */
 CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
                      const double* cams, const double* points, const int32_t* obs_cam,
-                     const int32_t* obs_pt, const double* obs_px, int precision,
+                     const int32_t* obs_pt, const double* obs_px, int mode,
                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* Run Levenberg-Marquardt from the current parameters (Sec. V).  opts may be

@@ -7,4 +7,4 @@ the C calls; every step of the solve runs in the HIP library.  Importing the
 package is cheap; the library is loaded on first use and its absence raises.
 """
 from .api import (BundleAdjuster, SolveOptions, BAFunction, project,  # noqa: F401
-                  FP64, FP32_MIXED, library_path)
+                  FP64, FP32_MIXED, RECOMPUTE_JACOBIAN, library_path)

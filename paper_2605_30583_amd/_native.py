@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcaspar_b
 FP64 = 0
 FP32_MIXED = 1
 ADJ_GAUGE_PROJECT = 1
+RECOMPUTE_JACOBIAN = 0x10
 STATUS = {0: "CASPAR_OK", -1: "CASPAR_EINVAL", -2: "CASPAR_EHIP", -3: "CASPAR_ENOMEM", -4: "CASPAR_ENUMERIC"}
 
 

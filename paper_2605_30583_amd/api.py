@@ -12,7 +12,7 @@ import dataclasses
 import torch
 
 from . import _native
-from ._native import FP64, FP32_MIXED, check
+from ._native import FP64, FP32_MIXED, RECOMPUTE_JACOBIAN, check
 
 library_path = _native.LIB_PATH
 
@@ -70,18 +70,21 @@ def project(cams: torch.Tensor, points: torch.Tensor, obs_cam: torch.Tensor, obs
 class BundleAdjuster:
     """One problem on one GPU (a caspar_ba handle plus its workspace)."""
 
-    def __init__(self, cams, points, obs_cam, obs_pt, obs_px, precision: int = FP64):
+    def __init__(self, cams, points, obs_cam, obs_pt, obs_px, precision: int = FP64,
+                 recompute_jacobian: bool = False):
         lib = _native.load()
         self._lib = lib
         self.n_cams, self.n_points, self.n_obs = int(cams.shape[0]), int(points.shape[0]), int(obs_cam.shape[0])
         self.device = cams.device
         self.precision = precision
+        self.recompute_jacobian = bool(recompute_jacobian)
+        mode = precision | (RECOMPUTE_JACOBIAN if recompute_jacobian else 0)
         _dev(cams, torch.float64, (self.n_cams, 9), "cams")
         _dev(points, torch.float64, (self.n_points, 3), "points")
         _dev(obs_cam, torch.int32, (self.n_obs,), "obs_cam")
         _dev(obs_pt, torch.int32, (self.n_obs,), "obs_pt")
         _dev(obs_px, torch.float64, (self.n_obs, 2), "obs_px")
-        nbytes = lib.caspar_ba_workspace_bytes(self.n_cams, self.n_points, self.n_obs, precision)
+        nbytes = lib.caspar_ba_workspace_bytes(self.n_cams, self.n_points, self.n_obs, mode)
         if nbytes == 0:
             raise ValueError("unsupported problem size or precision")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -91,7 +94,7 @@ class BundleAdjuster:
         self._ws_bytes = nbytes
         h = C.c_void_p()
         check(lib.caspar_ba_create(C.byref(h), self.n_cams, self.n_points, self.n_obs, _ptr(cams), _ptr(points),
-                                   _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), precision, self._ws_ptr,
+                                   _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), mode, self._ws_ptr,
                                    self._ws_bytes, _stream()))
         self._h = h
 
@@ -219,9 +222,9 @@ class BAFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, obs_px, cams0, points0, obs_cam, obs_pt, opts=None, precision=FP64, lambda_adj=1e-4,
-                adj_tol=1e-10, adj_max_iters=2000):
+                adj_tol=1e-10, adj_max_iters=2000, recompute_jacobian=False):
         ba = BundleAdjuster(cams0.detach().contiguous(), points0.detach().contiguous(), obs_cam, obs_pt,
-                            obs_px.detach().contiguous(), precision)
+                            obs_px.detach().contiguous(), precision, recompute_jacobian)
         stats = ba.solve(opts)
         cams, pts = ba.get_params()
         ctx.ba = ba
@@ -236,4 +239,4 @@ class BAFunction(torch.autograd.Function):
         gp = None if grad_points is None else grad_points.contiguous().to(torch.float64)
         g_obs = ctx.ba.backward(gc, gp, lam, tol, iters)
         ctx.ba.close()
-        return g_obs, None, None, None, None, None, None, None, None, None
+        return g_obs, None, None, None, None, None, None, None, None, None, None

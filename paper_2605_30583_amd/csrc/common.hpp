@@ -49,9 +49,9 @@ constexpr int kCamChunk = 2048;      // camera-major entries per linearisation c
 constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
 constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
 constexpr int kColdRow = 10;         // doubles per cold-camera row (9 sums, padded to 80 bytes)
-constexpr int kMvThreads = 1024;     // fused product: 16 waves per workgroup
-constexpr int kMvWaves = kMvThreads / kWave;
 constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
+constexpr int kPrivCams = 16;        // most observed cameras with private LDS copies in the product
+constexpr int kPrivCopies = 4;
 constexpr int kMaxHot = kLdsBudget / (9 * 8);  // 2048 cameras with float64 sums
 constexpr int kMaxPartials = 4096;   // per-workgroup partial slots
 constexpr int kPartialWidth = 4;     // doubles per partial slot
@@ -130,6 +130,7 @@ struct caspar_ba {
   int nc = 0, np = 0;
   int no = 0;
   int prec = CASPAR_FP64;
+  bool rj = false;        // Jacobian recomputed in every product instead of stored
   int N = 0;              // 9 nc + 3 np
   hipStream_t stream = nullptr;
   int device = 0;
@@ -149,6 +150,7 @@ struct caspar_ba {
   // parameters (float64, internal order)
   double* cam = nullptr;        // [nc][16]
   double* cam_trial = nullptr;
+  void* cam_s = nullptr;        // [nc][16] camera rows in the working precision (recomputed Jacobian)
   double* X = nullptr;          // [np][3]
   double* X_trial = nullptr;
 
@@ -217,14 +219,14 @@ struct Plan {
   struct Region {
     size_t off = 0, bytes = 0;
   };
-  Region cam, cam_trial, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+  Region cam, cam_trial, cam_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_perm, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;
 };
-bool make_plan(int nc, int np, int64_t no, int prec, Plan& plan);
+bool make_plan(int nc, int np, int64_t no, int mode, Plan& plan);
 
 inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
 
@@ -257,6 +259,7 @@ void timing_mark_start(caspar_ba* h);
 void timing_mark_stop(caspar_ba* h);
 void timing_harvest(caspar_ba* h, int effective);  // after a sync: count the first `effective` launches
 double matvec_algorithmic_bytes(const caspar_ba* h);
+int matvec_waves(int prec, bool rj);  // waves per workgroup of the fused product
 // helpers
 void sync(caspar_ba* h);
 DevScalars read_scalars(caspar_ba* h);

@@ -60,10 +60,12 @@ static int groups_per_cu(int K, int prec) {
   return lds > 80 * 1024 ? 1 : 2;
 }
 
-bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
+bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   if (nc < 0 || np < 0 || no < 0) return false;
   if (no >= (int64_t)1 << 31 || nc >= (1 << kCamBits)) return false;
-  if (prec != CASPAR_FP64 && prec != CASPAR_FP32_MIXED) return false;
+  if ((mode & ~(1 | CASPAR_RECOMPUTE_JACOBIAN)) != 0) return false;
+  const int prec = mode & 1;
+  const bool rj = (mode & CASPAR_RECOMPUTE_JACOBIAN) != 0;
   if (no > 0 && (nc == 0 || np == 0)) return false;
   if ((int64_t)9 * nc + 3 * (int64_t)np >= ((int64_t)1 << 31)) return false;
   const size_t s = scalar_bytes(prec);
@@ -92,6 +94,7 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
   take(p.gauge_rows, 256 * 35 * 8);
   take(p.cam, (size_t)nc * kCamStride * 8);
   take(p.cam_trial, (size_t)nc * kCamStride * 8);
+  take(p.cam_s, (size_t)nc * kCamStride * s);
   take(p.X, (size_t)np * 3 * 8);
   take(p.X_trial, (size_t)np * 3 * 8);
   take(p.cam_c2i, (size_t)nc * 4);
@@ -104,7 +107,7 @@ bool make_plan(int nc, int np, int64_t no, int prec, Plan& p) {
   // J doubles as the create-time scratch (sort buffers, counters).
   const size_t scratch = 2 * 8 * (size_t)no + 2 * 4 * (size_t)no + 4 * (size_t)no +
                          align_up(sort_bytes) + 8 * (size_t)np + 8 * (size_t)nc + 8192;
-  take(p.J, std::max(nch * no_pad * 16, scratch));
+  take(p.J, std::max(rj ? 0 : nch * no_pad * 16, scratch));
   take(p.tiles, p.max_tiles * sizeof(Tile));
   take(p.cold_perm, nc > p.K ? p.max_tiles * 64 : 64);
   take(p.p_cam, (size_t)nc * 80);  // 10 doubles or 12 floats per camera
@@ -553,7 +556,8 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   }
 
   // Fused-product grid.
-  h->G = std::max(1, std::min(groups_per_cu(h->K, h->prec) * kNumCUs, (h->n_tiles + kMvWaves - 1) / kMvWaves));
+  const int waves = matvec_waves(h->prec, h->rj);
+  h->G = std::max(1, std::min(groups_per_cu(h->K, h->prec) * kNumCUs, (h->n_tiles + waves - 1) / waves));
 
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);
@@ -602,23 +606,23 @@ void caspar_default_solve_opts(caspar_solve_opts* o) {
   o->flags = 0;
 }
 
-size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int precision) {
+size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int mode) {
   Plan p;
-  if (!make_plan(n_cams, n_points, n_obs, precision, p)) return 0;
+  if (!make_plan(n_cams, n_points, n_obs, mode, p)) return 0;
   return p.total;
 }
 
 int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
                      const double* cams, const double* points, const int32_t* obs_cam,
-                     const int32_t* obs_pt, const double* obs_px, int precision, void* workspace,
+                     const int32_t* obs_pt, const double* obs_px, int mode, void* workspace,
                      size_t workspace_bytes, void* hip_stream) {
   caspar_ba* h = nullptr;
   try {
     CBA_REQUIRE(out != nullptr, "out is NULL");
     *out = nullptr;
     Plan plan;
-    CBA_REQUIRE(make_plan(n_cams, n_points, n_obs, precision, plan),
-                "bad sizes or precision (n_obs < 2^31, n_cams < 2^25, observations need cameras and points)");
+    CBA_REQUIRE(make_plan(n_cams, n_points, n_obs, mode, plan),
+                "bad sizes or mode (n_obs < 2^31, n_cams < 2^25, observations need cameras and points)");
     if (workspace_bytes < plan.total)
       fail(CASPAR_ENOMEM, "workspace too small: need " + std::to_string(plan.total) + " bytes");
     CBA_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
@@ -630,7 +634,8 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->nc = n_cams;
     h->np = n_points;
     h->no = (int)n_obs;
-    h->prec = precision;
+    h->prec = mode & 1;
+    h->rj = (mode & CASPAR_RECOMPUTE_JACOBIAN) != 0;
     h->N = 9 * n_cams + 3 * n_points;
     h->stream = (hipStream_t)hip_stream;
     h->no_pad = (int)align_up((size_t)n_obs, kJBlock);
@@ -642,6 +647,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
     h->cam = (double*)(ws + plan.cam.off);
     h->cam_trial = (double*)(ws + plan.cam_trial.off);
+    h->cam_s = ws + plan.cam_s.off;
     h->X = (double*)(ws + plan.X.off);
     h->X_trial = (double*)(ws + plan.X_trial.off);
     h->cam_c2i = (int*)(ws + plan.cam_c2i.off);

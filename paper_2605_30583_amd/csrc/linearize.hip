@@ -20,10 +20,18 @@ __host__ __device__ constexpr int tri9(int k, int l) { return k * 9 - k * (k - 1
 
 __device__ inline double clamp_diag(double d) { return fmin(fmax(d, 1e-6), 1e32); }
 
+// Camera table in the working precision (used when the Jacobian is
+// recomputed; the conversion matches the one the linearisation applies).
+template <typename S>
+__global__ void k_cam_cast(int n, const double* __restrict__ cam, S* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (S)cam[i];
+}
+
 // ---------------------------------------------------------------------------
 // Point-major linearisation.
 // ---------------------------------------------------------------------------
-template <typename S>
+template <typename S, bool STORE_J>
 __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __restrict__ tiles,
                                                     const uint32_t* __restrict__ meta,
                                                     const double* __restrict__ px,
@@ -56,7 +64,7 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
       const double2 q = reinterpret_cast<const double2*>(px)[o];
       S r0, r1, col[12][2];
       snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
-      JStore<S>::store(J, o, col);
+      if (STORE_J) JStore<S>::store(J, o, col);
       cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
       double jp[3][2];
 #pragma unroll
@@ -288,10 +296,10 @@ __global__ void k_retract_points(int np, const double* __restrict__ X, const S* 
 // ---------------------------------------------------------------------------
 // Parity hook: residuals and Jacobian blocks in caller order, float64.
 // ---------------------------------------------------------------------------
-template <typename S>
+template <typename S, bool RJ>
 __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
                              const double* __restrict__ px, const double* __restrict__ cam,
-                             const double* __restrict__ X, const void* J,
+                             const double* __restrict__ X, const void* J, const S* __restrict__ cam_s,
                              const int* __restrict__ s2c, double* resid, double* jc, double* jp) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -313,7 +321,7 @@ __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const 
     resid[2 * c + 1] = r1;
   }
   S col[12][2];
-  JStore<S>::load(J, o, col);
+  jacobian_of<S, RJ>(J, cam_s, X, o, ci, pi, col);
   if (jc)
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 9; ++j) jc[18 * c + 9 * i + j] = col[j][i];
@@ -339,9 +347,18 @@ static void linearize_t(caspar_ba* h) {
   S* g = (S*)h->vec.g;
   S* D = (S*)h->vec.D;
   const unsigned tg = tile_grid(h->n_tiles);
+  if (h->rj && h->nc > 0) {
+    k_cam_cast<S><<<nblk((int64_t)h->nc * kCamStride, 256), 256, 0, st>>>(h->nc * kCamStride, h->cam,
+                                                                          (S*)h->cam_s);
+    CBA_LAUNCHED();
+  }
   if (h->n_tiles > 0) {
-    k_lin_points<S><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J,
-                                         g, D, h->Hpp, h->split_rows, h->nc, h->partials);
+    if (h->rj)
+      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, g, D,
+                                                 h->Hpp, h->split_rows, h->nc, h->partials);
+    else
+      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, g, D,
+                                                h->Hpp, h->split_rows, h->nc, h->partials);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
     CBA_LAUNCHED();
@@ -417,12 +434,21 @@ void run_retract(caspar_ba* h, const void* delta) {
 void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* jp) {
   if (h->n_tiles == 0) return;
   const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
-  if (h->prec == CASPAR_FP64)
-    k_export_lin<double><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
-                                                      h->J, h->obs_s2c, resid, jc, jp);
-  else
-    k_export_lin<float><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X,
-                                                     h->J, h->obs_s2c, resid, jc, jp);
+#define CBA_EXPORT(S, RJ)                                                                                 \
+  k_export_lin<S, RJ><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, \
+                                                   (const S*)h->cam_s, h->obs_s2c, resid, jc, jp)
+  if (h->prec == CASPAR_FP64) {
+    if (h->rj)
+      CBA_EXPORT(double, true);
+    else
+      CBA_EXPORT(double, false);
+  } else {
+    if (h->rj)
+      CBA_EXPORT(float, true);
+    else
+      CBA_EXPORT(float, false);
+  }
+#undef CBA_EXPORT
   CBA_LAUNCHED();
 }
 

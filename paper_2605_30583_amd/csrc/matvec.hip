@@ -60,21 +60,31 @@ __device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c
   }
 }
 
-// Launch shape of the fused product per precision: 16 waves per workgroup,
-// and the next tile's Jacobian chunks prefetched while the current tile is
+// Launch shape of the fused product: 16 waves per workgroup, and with stored
+// blocks the next tile's Jacobian chunks prefetched while the current tile is
 // computed (float32: 24 extra VGPRs; float64 prefetches only the meta word).
-template <typename S>
-struct MvCfg;
-template <>
-struct MvCfg<float> {
+// Recomputing float64 blocks needs more than 128 VGPRs, so that variant runs
+// 8-wave workgroups (256 VGPRs per lane).
+template <typename S, bool RJ>
+struct MvCfg {
   static constexpr int threads = 1024;
   static constexpr bool prefetch_j = true;
 };
 template <>
-struct MvCfg<double> {
+struct MvCfg<double, false> {
   static constexpr int threads = 1024;
   static constexpr bool prefetch_j = false;
 };
+template <>
+struct MvCfg<double, true> {
+  static constexpr int threads = 512;
+  static constexpr bool prefetch_j = false;
+};
+
+int matvec_waves(int prec, bool rj) {
+  if (prec == CASPAR_FP64) return (rj ? MvCfg<double, true>::threads : MvCfg<double, false>::threads) / kWave;
+  return (rj ? MvCfg<float, true>::threads : MvCfg<float, false>::threads) / kWave;
+}
 
 // Writes one cold row (9 sums, padded to kColdRow doubles: five 16-byte stores).
 __device__ inline void store_cold_row(double* row, const double v[9]) {
@@ -86,22 +96,27 @@ __device__ inline void store_cold_row(double* row, const double v[9]) {
   r[4] = make_double2(v[8], 0.0);
 }
 
-template <typename S, int THREADS, bool PREFETCH_J>
+template <typename S, int THREADS, bool PREFETCH_J, bool RJ>
 __global__ __launch_bounds__(THREADS) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-    const void* __restrict__ J, const S* __restrict__ p_cam, const uint8_t* __restrict__ cold_perm,
+    const void* __restrict__ J, const S* __restrict__ cam_s, const double* __restrict__ Xpts,
+    const S* __restrict__ p_cam, const uint8_t* __restrict__ cold_perm,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
-    double* __restrict__ partials, const DevScalars* __restrict__ sc) {
+    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P) {
   constexpr int WAVES = THREADS / kWave;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* hot = reinterpret_cast<double*>(lds_raw);  // [K][9]
+  double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
+  // the P most observed cameras get kPrivCopies private copies (copy = lane
+  // mod kPrivCopies), so lanes of one wave hitting the same camera mostly
+  // update different addresses; folded into hot[] before the flush
+  double* priv = hot + (size_t)K * 9;                      // [kPrivCopies][P][9]
   __shared__ double red[WAVES];
   if (sc != nullptr && sc->done) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  for (int i = tid; i < K * 9; i += THREADS) hot[i] = 0.0;
+  for (int i = tid; i < (K + kPrivCopies * P) * 9; i += THREADS) hot[i] = 0.0;
   __syncthreads();
 
   const S* __restrict__ pp_base = p + 9 * (size_t)nc;
@@ -112,30 +127,42 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
   const int t1 = (int)((int64_t)n_tiles * (blockIdx.x + 1) / G);
 
   // state of the current tile: descriptor, meta word, Jacobian columns
+  const bool has_cold = nc > K;
   int t = t0 + wv;
   Tile tl{};
   int n = 0;
   uint32_t m = 0;
+  int perm = lane;
   S col[12][2];
   if (t < t1) {
     tl = tiles[t];
     n = tile_nobs(tl.info);
     if (lane < n) {
       m = meta[tl.obs_begin + lane];
-      JStore<S>::load(J, tl.obs_begin + lane, col);
+      if (!RJ) JStore<S>::load(J, tl.obs_begin + lane, col);
     }
+    if (has_cold) perm = cold_perm[(size_t)t * kWave + lane];
   }
   for (; t < t1; t += WAVES) {
     const bool act = lane < n;
     const int ci = act ? (int)(m & ((1u << kCamBits) - 1)) : -1;
     const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
-    // 1. gathers of the current tile (camera row, point block)
+    // 1. gathers of the current tile (camera row, point block; with a
+    //    recomputed Jacobian also the camera parameters and the point)
     S pcv[CamPad<S>::n], pjv[3];
+    Cam<S> cpar;
+    S xj[3];
     if (act) {
       load_cam_row<S>(p_cam, ci, pcv);
       const S* pj = pp_base + 3 * (size_t)(tl.pt_begin + lp);
 #pragma unroll
       for (int k = 0; k < 3; ++k) pjv[k] = pj[k];
+      if (RJ) {
+        cpar = load_cam_s<S>(cam_s, ci);
+        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + lp);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
+      }
     }
     // 2. prefetch of the next tile, issued after the gathers so that waiting
     //    for the gathers does not wait for it
@@ -144,14 +171,16 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
     Tile tln{};
     int nn = 0;
     uint32_t mn = 0;
+    int permn = lane;
     S coln[12][2];
     if (tn < t1) {
       tln = tiles[tn];
       nn = tile_nobs(tln.info);
       if (lane < nn) {
         mn = meta[tln.obs_begin + lane];
-        if (PREFETCH_J) JStore<S>::load(J, tln.obs_begin + lane, coln);
+        if (PREFETCH_J && !RJ) JStore<S>::load(J, tln.obs_begin + lane, coln);
       }
+      if (has_cold) permn = cold_perm[(size_t)tn * kWave + lane];
     }
     __builtin_amdgcn_sched_barrier(0);
     // 3. the current tile
@@ -161,6 +190,10 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
 #pragma unroll
     for (int k = 0; k < 3; ++k) yp[k] = (S)0;
     if (act) {
+      if (RJ) {
+        S r0, r1;
+        snavely_jacobian<S>(cpar, xj[0], xj[1], xj[2], (S)0, (S)0, r0, r1, col);
+      }
       S q0 = (S)0, q1 = (S)0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
@@ -178,7 +211,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
 #pragma unroll
       for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
       if (ci < K) {
-        double* a = hot + 9 * ci;
+        double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9 : hot + 9 * ci;
 #pragma unroll
         for (int k = 0; k < 9; ++k) atomicAdd(a + k, (double)yc[k]);
       }
@@ -190,26 +223,31 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
     if (cm != 0ull) {
       const int ncold = __popcll(cm);
       const bool valid = lane < ncold;
-      const int src = valid ? (int)cold_perm[(size_t)t * kWave + lane] : lane;
+      const int src = valid ? perm : lane;
       int key = __shfl(ci, src, kWave);
       key = valid ? key : -1 - lane;
-      double v[9];
+      S v[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) v[k] = __shfl((double)yc[k], src, kWave);
+      for (int k = 0; k < 9; ++k) v[k] = __shfl(yc[k], src, kWave);
       for (int d = 1; d < kWave; d <<= 1) {
         const int okey = __shfl_down(key, d, kWave);
         const bool take = (lane + d < kWave) && okey == key;
         if (!__any(take)) break;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-          const double o = __shfl_down(v[k], d, kWave);
+          const S o = __shfl_down(v[k], d, kWave);
           if (take) v[k] += o;
         }
       }
       const int pkey = __shfl_up(key, 1, kWave);
       const bool head = valid && (lane == 0 || pkey != key);
       const unsigned long long hm = __ballot(head);
-      if (head) store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, v);
+      if (head) {
+        double vd[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vd[k] = (double)v[k];
+        store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, vd);
+      }
     }
     // points: segmented suffix sums, the first lane of each point holds the total
     const int steps = tile_steps(tl.info);
@@ -250,7 +288,10 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
     tl = tln;
     n = nn;
     m = mn;
-    if (PREFETCH_J) {
+    perm = permn;
+    if (RJ) {
+      // the next tile's blocks are evaluated from its gathers
+    } else if (PREFETCH_J) {
 #pragma unroll
       for (int j = 0; j < 12; ++j) {
         col[j][0] = coln[j][0];
@@ -269,8 +310,15 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
     const double v = pp_base[i];
     pap = fma(lambda * (double)dp_base[i] * v, v, pap);
   }
-  const double tot = block_sum(pap, red);
+  const double tot = block_sum(pap, red);  // (also orders the LDS updates before the fold)
   if (tid == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
+  for (int i = tid; i < P * 9; i += THREADS) {
+    double s = hot[i];
+#pragma unroll
+    for (int c = 0; c < kPrivCopies; ++c) s += priv[(size_t)c * P * 9 + i];
+    hot[i] = s;
+  }
+  __syncthreads();
   double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
   for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
 }
@@ -365,24 +413,34 @@ __global__ __launch_bounds__(256) void k_matvec_final(
   }
 }
 
+template <typename S, bool RJ>
+static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const DevScalars* scp) {
+  constexpr int T = MvCfg<S, RJ>::threads;
+  const int P = std::min(h->K, kPrivCams);
+  const size_t lds = ((size_t)h->K + (size_t)kPrivCopies * P) * 9 * sizeof(double);
+  auto kern = k_matvec<S, T, MvCfg<S, RJ>::prefetch_j, RJ>;
+  if (lds > 65536)
+    CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  timing_mark_start(h);
+  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, h->X,
+                                     (const S*)h->p_cam, h->cold_perm, p, (const S*)h->vec.D, lambda, w, h->nc,
+                                     h->K, h->n_orphan_pts, (double*)h->hot_rows, (double*)h->cold_rows,
+                                     h->split_rows, h->partials, scp, P);
+  CBA_LAUNCHED();
+  timing_mark_stop(h);
+}
+
 template <typename S>
 static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mode) {
   hipStream_t st = h->stream;
-  constexpr int T = MvCfg<S>::threads;
-  const size_t lds = (size_t)h->K * 9 * sizeof(double);
   const DevScalars* scp = pcg_mode ? h->scal : nullptr;
   if (h->n_tiles > 0 || h->nc > 0 || h->n_orphan_pts > 0) {
     k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(h->nc, p, (S*)h->p_cam, scp);
     CBA_LAUNCHED();
-    auto kern = k_matvec<S, T, MvCfg<S>::prefetch_j>;
-    if (lds > 65536)
-      CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget));
-    timing_mark_start(h);
-    kern<<<h->G, T, lds, st>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->p_cam, h->cold_perm, p,
-                               (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows,
-                               (double*)h->cold_rows, h->split_rows, h->partials, scp);
-    CBA_LAUNCHED();
-    timing_mark_stop(h);
+    if (h->rj)
+      launch_matvec<S, true>(h, lambda, p, w, scp);
+    else
+      launch_matvec<S, false>(h, lambda, p, w, scp);
   }
   const int nb_hot = (h->K * 9 + 63) / 64;
   const int nb_cold = (h->nc - h->K + 3) / 4;
@@ -397,12 +455,14 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   CBA_LAUNCHED();
 }
 
-// Bytes the fused product must move per launch: the Jacobian blocks and the
-// meta word of every observation, and p read, D read, w written once per
-// parameter.
+// Bytes the fused product must move per launch: the meta word of every
+// observation and, when stored, its Jacobian blocks; p read, D read and w
+// written once per parameter; with a recomputed Jacobian also the points'
+// coordinates (float64) once per point.
 double matvec_algorithmic_bytes(const caspar_ba* h) {
   const double s = (double)scalar_bytes(h->prec);
-  return (double)h->no * (24.0 * s + 4.0) + 3.0 * s * (double)h->N;
+  const double per_obs = h->rj ? 4.0 : 24.0 * s + 4.0;
+  return (double)h->no * per_obs + 3.0 * s * (double)h->N + (h->rj ? 24.0 * (double)h->np : 0.0);
 }
 
 void timing_mark_start(caspar_ba* h) {

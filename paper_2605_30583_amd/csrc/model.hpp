@@ -38,6 +38,38 @@ __device__ inline Cam<T> load_cam(const double* __restrict__ camtab, int c) {
   return cam;
 }
 
+// Camera row of the working-precision table (16 values: R t f k1 k2 pad),
+// read with 16-byte vector loads.
+template <typename T>
+__device__ inline Cam<T> load_cam_s(const T* __restrict__ tab, int c);
+template <>
+__device__ inline Cam<double> load_cam_s<double>(const double* __restrict__ tab, int c) {
+  return load_cam<double>(tab, c);
+}
+template <>
+__device__ inline Cam<float> load_cam_s<float>(const float* __restrict__ tab, int c) {
+  const float4* row = reinterpret_cast<const float4*>(tab + (size_t)c * kCamStride);
+  float v[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 q = row[i];
+    v[4 * i] = q.x;
+    v[4 * i + 1] = q.y;
+    v[4 * i + 2] = q.z;
+    v[4 * i + 3] = q.w;
+  }
+  Cam<float> cam;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cam.R[i] = v[i];
+  cam.t[0] = v[9];
+  cam.t[1] = v[10];
+  cam.t[2] = v[11];
+  cam.f = v[12];
+  cam.k1 = v[13];
+  cam.k2 = v[14];
+  return cam;
+}
+
 // Residual of one observation.  P = R X + t; the depth keeps its sign away
 // from zero (d + eps sign(d), sign(0) = +1); p = -P_xy / d;
 // radial = 1 + k1 |p|^2 + k2 |p|^4; r = f radial p - px.
@@ -281,5 +313,21 @@ struct JStore<float> {
     }
   }
 };
+
+// Jacobian columns of an observation, from the stored blocks or evaluated
+// again from the working-precision camera row and the point (bitwise the
+// values the linearisation produced).
+template <typename S, bool RJ>
+__device__ inline void jacobian_of(const void* J, const S* __restrict__ cam_s, const double* __restrict__ X,
+                                   int o, int ci, int pi, S col[12][2]) {
+  if (RJ) {
+    const Cam<S> c = load_cam_s<S>(cam_s, ci);
+    const double* Xp = X + 3 * (size_t)pi;
+    S r0, r1;
+    snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)0, (S)0, r0, r1, col);
+  } else {
+    JStore<S>::load(J, o, col);
+  }
+}
 
 }  // namespace cba

@@ -125,9 +125,10 @@ __global__ void k_gauge_apply(int nc, int np, const double* __restrict__ cam, co
 }
 
 // dL/dpx_o = J_o v in caller order.
-template <typename S>
+template <typename S, bool RJ>
 __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-                              const void* __restrict__ J, const S* __restrict__ v, int nc,
+                              const void* __restrict__ J, const S* __restrict__ cam_s,
+                              const double* __restrict__ X, const S* __restrict__ v, int nc,
                               const int* __restrict__ s2c, double* __restrict__ out) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -139,7 +140,7 @@ __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const
   const int ci = (int)(m & ((1u << kCamBits) - 1));
   const int pi = tl.pt_begin + (int)(m >> kCamBits);
   S col[12][2];
-  JStore<S>::load(J, o, col);
+  jacobian_of<S, RJ>(J, cam_s, X, o, ci, pi, col);
   double q0 = 0.0, q1 = 0.0;
   for (int k = 0; k < 9; ++k) {
     const double x = v[9 * (size_t)ci + k];
@@ -260,8 +261,13 @@ static void adjoint_rhs_t(caspar_ba* h, const double* gc, const double* gp) {
 template <typename S>
 static void adjoint_obs_t(caspar_ba* h, double* out) {
   if (h->n_tiles == 0) return;
-  k_adjoint_obs<S><<<nblk((int64_t)h->n_tiles * kWave, 256), 256, 0, h->stream>>>(
-      h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+  const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
+  if (h->rj)
+    k_adjoint_obs<S, true><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->cam_s,
+                                                        h->X, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+  else
+    k_adjoint_obs<S, false><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->cam_s,
+                                                         h->X, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
   CBA_LAUNCHED();
 }
 

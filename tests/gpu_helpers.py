@@ -38,11 +38,11 @@ def ragged_scene(seed=13):
     return Scene(cams, pts, oc.astype(np.int32), op.astype(np.int32), noise, cams0, pts0)
 
 
-def handle_for(sc, px, precision=0, cams=None, points=None):
+def handle_for(sc, px, precision=0, cams=None, points=None, rj=False):
     from paper_2605_30583_amd import BundleAdjuster
     return BundleAdjuster(t64(sc.cams_init if cams is None else cams),
                           t64(sc.points_init if points is None else points),
-                          t32i(sc.obs_cam), t32i(sc.obs_pt), t64(px), precision)
+                          t32i(sc.obs_cam), t32i(sc.obs_pt), t64(px), precision, recompute_jacobian=rj)
 
 
 @dataclasses.dataclass

@@ -56,10 +56,11 @@ def _subset_reference(sc, px, st0, cams, pts, lam, p):
 # (u = 2^-53) relative to the sum of magnitudes, so the gate is 1e-10 (the
 # 1e-12 gate applies where the oracle takes the whole problem, at the small
 # sizes).  float32-mixed: products and sums in float32.
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-5)])
-def test_large_workload_cost_gradient_and_product(large, precision, tol):
+def test_large_workload_cost_gradient_and_product(large, precision, tol, rj):
     sc, px, st0, cost, cams, pts = large
-    ba = handle_for(sc, px, precision)
+    ba = handle_for(sc, px, precision, rj=rj)
     info = ba.layout_info()
     assert info["hot_cams"] == 2048
     assert info["cold_obs"] > 0 and info["matvec_groups"] == 256

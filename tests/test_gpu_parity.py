@@ -18,13 +18,15 @@ SCENES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(SCENES))
+@pytest.fixture(scope="module", params=[(s, rj) for rj in (False, True) for s in SCENES],
+                ids=lambda p: f"{p[0]}-{'recompute' if p[1] else 'stored'}")
 def case(request):
-    sc = SCENES[request.param]()
+    name, rj = request.param
+    sc = SCENES[name]()
     px = observed_pixels(sc)
-    ba = handle_for(sc, px)
+    ba = handle_for(sc, px, rj=rj)
     ref = oracle_lin(sc, px)
-    yield request.param, sc, px, ba, ref
+    yield name, sc, px, ba, ref
     ba.close()
 
 
@@ -133,13 +135,14 @@ def test_create_rejects_bad_inputs():
         handle_for(sc, pxn)
 
 
+@pytest.mark.parametrize("rj", [False, True])
 @pytest.mark.parametrize("zipf", [None, 0.9])
-def test_cold_camera_rows_and_full_lds(zipf):
+def test_cold_camera_rows_and_full_lds(zipf, rj):
     # more cameras than the LDS holds: the least observed ones go through rows
     from synth import make_scene
     sc = make_scene(2300, 6000, 17, k_values=(2, 3, 4), k_probs=(0.3, 0.4, 0.3), zipf_s=zipf)
     px = observed_pixels(sc)
-    ba = handle_for(sc, px)
+    ba = handle_for(sc, px, rj=rj)
     info = ba.layout_info()
     assert info["hot_cams"] == 2048 and info["cold_obs"] > 0      # float64: 2048 cameras in LDS
     ref = oracle_lin(sc, px)
@@ -154,14 +157,15 @@ def test_cold_camera_rows_and_full_lds(zipf):
         assert abs(pap - p @ w_ref) <= 1e-12 * abs(p @ w_ref)
 
 
-def test_mixed_precision_cold_rows_and_products():
+@pytest.mark.parametrize("rj", [False, True])
+def test_mixed_precision_cold_rows_and_products(rj):
     # float32-mixed with cameras outside the LDS set; Zipf-skewed visibility
     # with points grouped by their least observed camera, so several
     # observations of one cold camera share a tile and a row
     from synth import make_scene
     sc = make_scene(5000, 20000, 19, k_values=(3, 4), k_probs=(0.5, 0.5), zipf_s=0.8)
     px = observed_pixels(sc)
-    ba = handle_for(sc, px, precision=1)
+    ba = handle_for(sc, px, precision=1, rj=rj)
     info = ba.layout_info()
     assert info["hot_cams"] == 2048 and info["cold_obs"] > 0
     ref = oracle_lin(sc, px)

@@ -18,18 +18,19 @@ pytestmark = pytest.mark.gpu
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lm_reference.json")))["runs"]
 
 
-def _solve(name, precision=0, tol=1e-6):
+def _solve(name, precision=0, tol=1e-6, rj=False):
     from paper_2605_30583_amd import SolveOptions
     sc = scene_config(name)
     px = observed_pixels(sc)
-    ba = handle_for(sc, px, precision)
+    ba = handle_for(sc, px, precision, rj=rj)
     stats = ba.solve(SolveOptions(max_lm_iters=GOLDEN[name]["max_iters"], pcg_tol=tol), history=True)
     return sc, px, ba, stats
 
 
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
 @pytest.mark.parametrize("name", ["tiny", "medium", "bal1700"])
-def test_fp64_final_cost_matches_oracle(name):
-    sc, px, ba, st = _solve(name)
+def test_fp64_final_cost_matches_oracle(name, rj):
+    sc, px, ba, st = _solve(name, rj=rj)
     g = GOLDEN[name]
     assert abs(st["initial_cost"] - g["initial_cost"]) <= 1e-12 * g["initial_cost"]
     assert abs(st["final_cost"] - g["final_cost"]) <= 1e-9 * g["final_cost"], (st["final_cost"], g["final_cost"])
@@ -46,9 +47,10 @@ def test_fp64_final_cost_matches_oracle(name):
     assert abs(camera.cost(st_o, sc.obs_cam, sc.obs_pt, px) - st["final_cost"]) <= 1e-10 * st["final_cost"]
 
 
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
 @pytest.mark.parametrize("name", ["tiny", "bal1700"])
-def test_fp32_mixed_final_cost_error_is_small(name):
-    sc, px, ba, st = _solve(name, precision=1)
+def test_fp32_mixed_final_cost_error_is_small(name, rj):
+    sc, px, ba, st = _solve(name, precision=1, rj=rj)
     f64 = ba.cost_fp64()
     g = GOLDEN[name]["final_cost"]
     # stated, not a parity claim: the mixed form, re-evaluated in float64,
@@ -73,8 +75,9 @@ def test_warm_restart_continues_from_set_params():
     assert abs(s2["final_cost"] - GOLDEN["tiny"]["final_cost"]) <= 1e-9 * GOLDEN["tiny"]["final_cost"]
 
 
-def test_adjoint_matches_oracle_implicit_gradient():
-    sc, px, ba, st = _solve("tiny")
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
+def test_adjoint_matches_oracle_implicit_gradient(rj):
+    sc, px, ba, st = _solve("tiny", rj=rj)
     cams, pts = ba.get_params()
     state = camera.State.from_bal(cams.cpu().numpy(), pts.cpu().numpy())
     g = adjoint.point_norm_loss_grad(state)
