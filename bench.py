@@ -111,7 +111,7 @@ def cpu_baseline(sc, n_points: int, pcg_tol: float):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (no multi-GPU path in this build)",
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the library runs on a single GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch

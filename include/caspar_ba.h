@@ -220,7 +220,11 @@ CASPAR_API int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* c
 typedef struct caspar_timing {
   int64_t matvec_launches;  /* fused-product launches that did work */
   double matvec_ms;         /* summed duration of those launches (event time) */
-  double matvec_bytes;      /* algorithmic bytes of one launch (see DESIGN notes) */
+  double matvec_bytes;      /* bytes one launch must move: per observation the
+                               24 Jacobian scalars (stored mode) and two int32
+                               indices; per parameter p and D read, w written;
+                               recompute mode adds the camera rows and the
+                               float64 points instead of the blocks */
 } caspar_timing;
 
 /* enable != 0 starts (and zeroes) the counters; 0 stops them. */

@@ -7,7 +7,7 @@ preconditioner with one block per node (Section V: one block per pose or
 landmark), and the exact step by dense Cholesky or by the Schur complement
 on the cameras.
 
-Readings: D = diag(J^T J) clamped to [1e-6, 1e32]; the
+Readings where the paper leaves it open: D = diag(J^T J) clamped to [1e-6, 1e32]; the
 preconditioner blocks are the diagonal blocks of J^T J + lambda D.
 
 Pins (tests/test_oracle_linear.py): matvec vs a dense J^T J product built

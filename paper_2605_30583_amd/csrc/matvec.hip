@@ -459,12 +459,6 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
 // observation and, when stored, its Jacobian blocks; p read, D read and w
 // written once per parameter; with a recomputed Jacobian also the points'
 // coordinates (float64) once per point.
-double matvec_algorithmic_bytes(const caspar_ba* h) {
-  const double s = (double)scalar_bytes(h->prec);
-  const double per_obs = h->rj ? 4.0 : 24.0 * s + 4.0;
-  return (double)h->no * per_obs + 3.0 * s * (double)h->N + (h->rj ? 24.0 * (double)h->np : 0.0);
-}
-
 void timing_mark_start(caspar_ba* h) {
   if (!h->timing) return;
   if (h->ev_used == (int)h->ev_start.size()) {

@@ -331,6 +331,19 @@ static void gauge_project_t(caspar_ba* h) {
   CBA_LAUNCHED();
 }
 
+// Bytes the damped normal-equation product must move per launch, the figure
+// its HBM roofline is priced on.  With stored blocks: per observation the
+// 2x9 and 2x3 blocks (24 scalars) and two int32 indices; per parameter p and
+// D read and w written.  With recomputed blocks the observation keeps only
+// its two indices and the product reads the camera rows (16 scalars) and the
+// float64 points instead.
+double matvec_algorithmic_bytes(const caspar_ba* h) {
+  const double s = (double)scalar_bytes(h->prec);
+  const double per_param = 3.0 * s * (double)h->N;
+  if (!h->rj) return (double)h->no * (24.0 * s + 8.0) + per_param;
+  return (double)h->no * 8.0 + per_param + 24.0 * (double)h->np + 16.0 * s * (double)h->nc;
+}
+
 }  // namespace cba
 
 using namespace cba;
