@@ -60,25 +60,37 @@ __device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c
   }
 }
 
-// Launch shape of the fused product: 16 waves per workgroup, and with stored
-// blocks the next tile's Jacobian chunks prefetched while the current tile is
-// computed (float32: 24 extra VGPRs; float64 prefetches only the meta word).
-// Recomputing float64 blocks needs more than 128 VGPRs, so that variant runs
-// 8-wave workgroups (256 VGPRs per lane).
+// Launch shape and pipeline depth of the fused product.  16 waves per
+// workgroup; recomputing float64 blocks needs more than 128 VGPRs, so that
+// variant runs 8-wave workgroups (256 VGPRs per lane).  One tile ahead of the
+// one being computed, the product requests
+//   prefetch_j:   the stored Jacobian chunks (float32: 24 VGPRs; float64 has
+//                 no room and loads them at the end of the previous tile);
+//   prefetch_pt:  p and D of the tile's points (otherwise loaded with the
+//                 camera gathers of the tile itself);
+//   prefetch_cam: the camera rows of p and, with recomputed blocks, the
+//                 camera parameters and the point (otherwise gathered at the
+//                 start of the tile, with their latency exposed).
 template <typename S, bool RJ>
 struct MvCfg {
   static constexpr int threads = 1024;
   static constexpr bool prefetch_j = true;
+  static constexpr bool prefetch_pt = true;
+  static constexpr bool prefetch_cam = true;
 };
 template <>
 struct MvCfg<double, false> {
   static constexpr int threads = 1024;
   static constexpr bool prefetch_j = false;
+  static constexpr bool prefetch_pt = false;
+  static constexpr bool prefetch_cam = false;
 };
 template <>
 struct MvCfg<double, true> {
   static constexpr int threads = 512;
   static constexpr bool prefetch_j = false;
+  static constexpr bool prefetch_pt = true;
+  static constexpr bool prefetch_cam = true;
 };
 
 int matvec_waves(int prec, bool rj) {
@@ -96,15 +108,19 @@ __device__ inline void store_cold_row(double* row, const double v[9]) {
   r[4] = make_double2(v[8], 0.0);
 }
 
-template <typename S, int THREADS, bool PREFETCH_J, bool RJ>
-__global__ __launch_bounds__(THREADS) void k_matvec(
+template <typename S, bool RJ>
+__global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
     const void* __restrict__ J, const S* __restrict__ cam_s, const double* __restrict__ Xpts,
     const S* __restrict__ p_cam, const uint8_t* __restrict__ cold_perm,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
     double* __restrict__ partials, const DevScalars* __restrict__ sc, int P) {
+  constexpr int THREADS = MvCfg<S, RJ>::threads;
   constexpr int WAVES = THREADS / kWave;
+  constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
+  constexpr bool PF_PT = MvCfg<S, RJ>::prefetch_pt;
+  constexpr bool PF_CAM = MvCfg<S, RJ>::prefetch_cam;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
   // the P most observed cameras get kPrivCopies private copies (copy = lane
@@ -126,179 +142,252 @@ __global__ __launch_bounds__(THREADS) void k_matvec(
   const int t0 = (int)((int64_t)n_tiles * blockIdx.x / G);
   const int t1 = (int)((int64_t)n_tiles * (blockIdx.x + 1) / G);
 
-  // state of the current tile: descriptor, meta word, Jacobian columns
+  // Software pipeline over the wave's tiles t, t + W, t + 2W, t + 3W (W =
+  // waves per workgroup):
+  //   tile t       being computed: meta word, Jacobian columns, p and D of
+  //                its points, the camera rows of p and the cold permutation
+  //                are in registers (whatever the configuration does not
+  //                prefetch is gathered at the start of the tile);
+  //   tile t + W   meta in registers; its Jacobian columns, point data,
+  //                camera rows and permutation are requested during tile t;
+  //   tile t + 2W  meta requested during tile t;
+  //   tile t + 3W  descriptor requested during tile t.
+  // The tile index is wave-uniform, so descriptors come through the scalar
+  // cache.  Every vector load is issued unconditionally (lanes past a tile's
+  // end, and tiles past the range, read clamped in-range addresses and
+  // their values are unused), so each iteration issues a fixed number of
+  // loads and every wait covers exactly the loads it needs.
   const bool has_cold = nc > K;
-  int t = t0 + wv;
-  Tile tl{};
-  int n = 0;
-  uint32_t m = 0;
-  int perm = lane;
-  S col[12][2];
+  int t = t0 + __builtin_amdgcn_readfirstlane(wv);
   if (t < t1) {
-    tl = tiles[t];
-    n = tile_nobs(tl.info);
-    if (lane < n) {
-      m = meta[tl.obs_begin + lane];
-      if (!RJ) JStore<S>::load(J, tl.obs_begin + lane, col);
+    auto nobs = [&](int ti, const Tile& T) { return ti < t1 ? tile_nobs(T.info) : 0; };
+    auto olane = [&](int k) { return min(lane, max(k, 1) - 1); };
+    auto tile_at = [&](int ti) { return tiles[min(ti, t1 - 1)]; };
+    auto perm_at = [&](int ti) {
+      return (int)cold_perm[has_cold ? (size_t)min(ti, t1 - 1) * kWave + lane : (size_t)lane];
+    };
+    Tile tl = tiles[t], tln = tile_at(t + WAVES), tlnn = tile_at(t + 2 * WAVES);
+    int n = tile_nobs(tl.info);
+    uint32_t m = meta[tl.obs_begin + olane(n)];
+    uint32_t mn = meta[tln.obs_begin + olane(nobs(t + WAVES, tln))];
+    S col[12][2];
+    if (!RJ) JStore<S>::load(J, tl.obs_begin + olane(n), col);
+    S pjv[3], dpv[3];
+    if (PF_PT) {
+      const size_t b = 3 * (size_t)(tl.pt_begin + (int)(m >> kCamBits));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        pjv[k] = pp_base[b + k];
+        dpv[k] = dp_base[b + k];
+      }
     }
-    if (has_cold) perm = cold_perm[(size_t)t * kWave + lane];
-  }
-  for (; t < t1; t += WAVES) {
-    const bool act = lane < n;
-    const int ci = act ? (int)(m & ((1u << kCamBits) - 1)) : -1;
-    const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
-    // 1. gathers of the current tile (camera row, point block; with a
-    //    recomputed Jacobian also the camera parameters and the point)
-    S pcv[CamPad<S>::n], pjv[3];
+    S pcv[CamPad<S>::n];
     Cam<S> cpar;
     S xj[3];
-    if (act) {
-      load_cam_row<S>(p_cam, ci, pcv);
-      const S* pj = pp_base + 3 * (size_t)(tl.pt_begin + lp);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) pjv[k] = pj[k];
+    if (PF_CAM) {
+      load_cam_row<S>(p_cam, (int)(m & ((1u << kCamBits) - 1)), pcv);
       if (RJ) {
-        cpar = load_cam_s<S>(cam_s, ci);
-        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + lp);
+        cpar = load_cam_s<S>(cam_s, (int)(m & ((1u << kCamBits) - 1)));
+        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + (int)(m >> kCamBits));
 #pragma unroll
         for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
       }
     }
-    // 2. prefetch of the next tile, issued after the gathers so that waiting
-    //    for the gathers does not wait for it
-    __builtin_amdgcn_sched_barrier(0);
-    const int tn = t + WAVES;
-    Tile tln{};
-    int nn = 0;
-    uint32_t mn = 0;
-    int permn = lane;
-    S coln[12][2];
-    if (tn < t1) {
-      tln = tiles[tn];
-      nn = tile_nobs(tln.info);
-      if (lane < nn) {
-        mn = meta[tln.obs_begin + lane];
-        if (PREFETCH_J && !RJ) JStore<S>::load(J, tln.obs_begin + lane, coln);
-      }
-      if (has_cold) permn = cold_perm[(size_t)tn * kWave + lane];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // 3. the current tile
-    S yc[9], yp[3];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) yc[k] = (S)0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) yp[k] = (S)0;
-    if (act) {
-      if (RJ) {
-        S r0, r1;
-        snavely_jacobian<S>(cpar, xj[0], xj[1], xj[2], (S)0, (S)0, r0, r1, col);
-      }
-      S q0 = (S)0, q1 = (S)0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        q0 = fma(col[k][0], pcv[k], q0);
-        q1 = fma(col[k][1], pcv[k], q1);
-      }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        q0 = fma(col[9 + k][0], pjv[k], q0);
-        q1 = fma(col[9 + k][1], pjv[k], q1);
-      }
-      pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
-#pragma unroll
-      for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
-      if (ci < K) {
-        double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9 : hot + 9 * ci;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) atomicAdd(a + k, (double)yc[k]);
-      }
-    }
-    // cameras outside the LDS set: the tile's cold lanes, gathered in camera
-    // order, sum runs of one camera; each run's first lane writes its row
-    const bool cold = act && ci >= K;
-    const unsigned long long cm = __ballot(cold);
-    if (cm != 0ull) {
-      const int ncold = __popcll(cm);
-      const bool valid = lane < ncold;
-      const int src = valid ? perm : lane;
-      int key = __shfl(ci, src, kWave);
-      key = valid ? key : -1 - lane;
-      S v[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v[k] = __shfl(yc[k], src, kWave);
-      for (int d = 1; d < kWave; d <<= 1) {
-        const int okey = __shfl_down(key, d, kWave);
-        const bool take = (lane + d < kWave) && okey == key;
-        if (!__any(take)) break;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const S o = __shfl_down(v[k], d, kWave);
-          if (take) v[k] += o;
-        }
-      }
-      const int pkey = __shfl_up(key, 1, kWave);
-      const bool head = valid && (lane == 0 || pkey != key);
-      const unsigned long long hm = __ballot(head);
-      if (head) {
-        double vd[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) vd[k] = (double)v[k];
-        store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, vd);
-      }
-    }
-    // points: segmented suffix sums, the first lane of each point holds the total
-    const int steps = tile_steps(tl.info);
-    for (int s = 0, d = 1; s < steps; ++s, d <<= 1) {
-      const int olp = __shfl_down(lp, d, kWave);
-      const bool take = (lane + d < kWave) && olp == lp;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const S o = __shfl_down(yp[k], d, kWave);
-        if (take) yp[k] += o;
-      }
-    }
-    const int prev = __shfl_up(lp, 1, kWave);
-    const bool head = act && (lane == 0 || prev != lp);
-    if (head) {
-      const size_t b = 3 * (size_t)(tl.pt_begin + lp);
-      if (tile_split(tl.info)) {
-        double* row = split_rows + (size_t)tl.split_row * kPtRowWidth;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) row[k] = (double)yp[k];
-        if (tile_first(tl.info)) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const double v = pjv[k];
-            pap = fma(lambda * (double)dp_base[b + k] * v, v, pap);
-          }
-        }
-      } else {
+    int perm = perm_at(t);
+    for (;;) {
+      const bool act = lane < n;
+      const int ci_raw = (int)(m & ((1u << kCamBits) - 1));
+      const int lp_raw = (int)(m >> kCamBits);
+      const int ci = act ? ci_raw : -1;
+      const int lp = act ? lp_raw : 100 + lane;
+      // 1. gathers of the current tile: the camera row of p (with a
+      //    recomputed Jacobian also the camera parameters and the point;
+      //    without point prefetch also p and D of the point)
+      if (!PF_CAM) load_cam_row<S>(p_cam, ci_raw, pcv);
+      if (!PF_PT) {
+        const size_t b = 3 * (size_t)(tl.pt_begin + lp_raw);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const S dv = dp_base[b + k];
-          wp_base[b + k] = fma((S)lambda * dv, pjv[k], yp[k]);
-          pap = fma(lambda * (double)dv * (double)pjv[k], (double)pjv[k], pap);
+          pjv[k] = pp_base[b + k];
+          dpv[k] = dp_base[b + k];
         }
       }
-    }
-    // 4. advance
-    tl = tln;
-    n = nn;
-    m = mn;
-    perm = permn;
-    if (RJ) {
-      // the next tile's blocks are evaluated from its gathers
-    } else if (PREFETCH_J) {
+      if (RJ && !PF_CAM) {
+        cpar = load_cam_s<S>(cam_s, ci_raw);
+        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + lp_raw);
 #pragma unroll
-      for (int j = 0; j < 12; ++j) {
-        col[j][0] = coln[j][0];
-        col[j][1] = coln[j][1];
+        for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
       }
-    } else if (lane < nn) {
-      JStore<S>::load(J, tln.obs_begin + lane, col);
+      // 2. requests for the next tiles, issued after the gathers so that
+      //    waiting for the gathers does not wait for them
+      __builtin_amdgcn_sched_barrier(0);
+      const int tn = t + WAVES;
+      const int on = tln.obs_begin + olane(nobs(tn, tln));
+      S coln[12][2];
+      if (PREFETCH_J && !RJ) JStore<S>::load(J, on, coln);
+      S pjn[3], dpn[3];
+      if (PF_PT) {
+        const size_t b = 3 * (size_t)(tln.pt_begin + (int)(mn >> kCamBits));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          pjn[k] = pp_base[b + k];
+          dpn[k] = dp_base[b + k];
+        }
+      }
+      S pcvn[CamPad<S>::n];
+      Cam<S> cparn;
+      double xjn[3];
+      if (PF_CAM) {
+        const int cin = (int)(mn & ((1u << kCamBits) - 1));
+        load_cam_row<S>(p_cam, cin, pcvn);
+        if (RJ) {
+          cparn = load_cam_s<S>(cam_s, cin);
+          const double* Xp = Xpts + 3 * (size_t)(tln.pt_begin + (int)(mn >> kCamBits));
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xjn[k] = Xp[k];
+        }
+      }
+      const int permn = perm_at(tn);
+      const uint32_t mnn = meta[tlnn.obs_begin + olane(nobs(tn + WAVES, tlnn))];
+      const Tile tl3 = tile_at(tn + 2 * WAVES);
+      __builtin_amdgcn_sched_barrier(0);
+      // 3. the current tile
+      S yc[9], yp[3];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) yc[k] = (S)0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) yp[k] = (S)0;
+      if (act) {
+        if (RJ) {
+          S r0, r1;
+          snavely_jacobian<S>(cpar, xj[0], xj[1], xj[2], (S)0, (S)0, r0, r1, col);
+        }
+        S q0 = (S)0, q1 = (S)0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          q0 = fma(col[k][0], pcv[k], q0);
+          q1 = fma(col[k][1], pcv[k], q1);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          q0 = fma(col[9 + k][0], pjv[k], q0);
+          q1 = fma(col[9 + k][1], pjv[k], q1);
+        }
+        pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
+        if (ci < K) {
+          double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9 : hot + 9 * ci;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) atomicAdd(a + k, (double)yc[k]);
+        }
+      }
+      // cameras outside the LDS set: the tile's cold lanes, gathered in camera
+      // order, sum runs of one camera; each run's first lane writes its row
+      const bool cold = act && ci >= K;
+      const unsigned long long cm = __ballot(cold);
+      if (cm != 0ull) {
+        const int ncold = __popcll(cm);
+        const bool valid = lane < ncold;
+        const int src = valid ? perm : lane;
+        int key = __shfl(ci, src, kWave);
+        key = valid ? key : -1 - lane;
+        S v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = __shfl(yc[k], src, kWave);
+        for (int d = 1; d < kWave; d <<= 1) {
+          const int okey = __shfl_down(key, d, kWave);
+          const bool take = (lane + d < kWave) && okey == key;
+          if (!__any(take)) break;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const S o = __shfl_down(v[k], d, kWave);
+            if (take) v[k] += o;
+          }
+        }
+        const int pkey = __shfl_up(key, 1, kWave);
+        const bool head = valid && (lane == 0 || pkey != key);
+        const unsigned long long hm = __ballot(head);
+        if (head) {
+          double vd[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) vd[k] = (double)v[k];
+          store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, vd);
+        }
+      }
+      // points: segmented suffix sums, the first lane of each point holds the total
+      const int steps = tile_steps(tl.info);
+      for (int s = 0, d = 1; s < steps; ++s, d <<= 1) {
+        const int olp = __shfl_down(lp, d, kWave);
+        const bool take = (lane + d < kWave) && olp == lp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const S o = __shfl_down(yp[k], d, kWave);
+          if (take) yp[k] += o;
+        }
+      }
+      const int prev = __shfl_up(lp, 1, kWave);
+      const bool head = act && (lane == 0 || prev != lp);
+      if (head) {
+        const size_t b = 3 * (size_t)(tl.pt_begin + lp);
+        if (tile_split(tl.info)) {
+          double* row = split_rows + (size_t)tl.split_row * kPtRowWidth;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) row[k] = (double)yp[k];
+          if (tile_first(tl.info)) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              const double v = pjv[k];
+              pap = fma(lambda * (double)dpv[k] * v, v, pap);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            wp_base[b + k] = fma((S)lambda * dpv[k], pjv[k], yp[k]);
+            pap = fma(lambda * (double)dpv[k] * (double)pjv[k], (double)pjv[k], pap);
+          }
+        }
+      }
+      // 4. advance
+      t = tn;
+      if (t >= t1) break;
+      tl = tln;
+      n = nobs(t, tl);
+      m = mn;
+      perm = permn;
+      tln = tlnn;
+      mn = mnn;
+      tlnn = tl3;
+      if (PF_PT) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          pjv[k] = pjn[k];
+          dpv[k] = dpn[k];
+        }
+      }
+      if (PF_CAM) {
+#pragma unroll
+        for (int k = 0; k < CamPad<S>::n; ++k) pcv[k] = pcvn[k];
+        if (RJ) {
+          cpar = cparn;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xj[k] = (S)xjn[k];
+        }
+      }
+      if (RJ) {
+        // the next tile's blocks are evaluated from its gathers
+      } else if (PREFETCH_J) {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          col[j][0] = coln[j][0];
+          col[j][1] = coln[j][1];
+        }
+      } else {
+        JStore<S>::load(J, tl.obs_begin + olane(n), col);
+      }
     }
   }
   // lambda p^T D p of the camera blocks and of points without observations
@@ -418,7 +507,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
   constexpr int T = MvCfg<S, RJ>::threads;
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = ((size_t)h->K + (size_t)kPrivCopies * P) * 9 * sizeof(double);
-  auto kern = k_matvec<S, T, MvCfg<S, RJ>::prefetch_j, RJ>;
+  auto kern = k_matvec<S, RJ>;
   if (lds > 65536)
     CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   timing_mark_start(h);
@@ -455,10 +544,7 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   CBA_LAUNCHED();
 }
 
-// Bytes the fused product must move per launch: the meta word of every
-// observation and, when stored, its Jacobian blocks; p read, D read and w
-// written once per parameter; with a recomputed Jacobian also the points'
-// coordinates (float64) once per point.
+// HIP events around each launch of the fused product (when enabled).
 void timing_mark_start(caspar_ba* h) {
   if (!h->timing) return;
   if (h->ev_used == (int)h->ev_start.size()) {
