@@ -244,7 +244,7 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  /
 void run_retract(caspar_ba* h, const void* delta);  // trial = current (+) delta
 void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* jp);
 // matvec.hip
-void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool scalar_alpha);
+void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode, bool pad_cams = true);
 // pcg.hip
 void run_block_jacobi(caspar_ba* h, double lambda);
 void run_bj_apply(caspar_ba* h, const void* r, void* z);

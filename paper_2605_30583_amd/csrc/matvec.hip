@@ -520,12 +520,14 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
 }
 
 template <typename S>
-static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mode) {
+static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mode, bool pad_cams) {
   hipStream_t st = h->stream;
   const DevScalars* scp = pcg_mode ? h->scal : nullptr;
   if (h->n_tiles > 0 || h->nc > 0 || h->n_orphan_pts > 0) {
-    k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(h->nc, p, (S*)h->p_cam, scp);
-    CBA_LAUNCHED();
+    if (pad_cams) {
+      k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(h->nc, p, (S*)h->p_cam, scp);
+      CBA_LAUNCHED();
+    }
     if (h->rj)
       launch_matvec<S, true>(h, lambda, p, w, scp);
     else
@@ -576,11 +578,11 @@ void timing_harvest(caspar_ba* h, int effective) {
   h->ev_used = 0;
 }
 
-void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode) {
+void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode, bool pad_cams) {
   if (h->prec == CASPAR_FP64)
-    matvec_t<double>(h, lambda, (const double*)p, (double*)w, pcg_mode);
+    matvec_t<double>(h, lambda, (const double*)p, (double*)w, pcg_mode, pad_cams);
   else
-    matvec_t<float>(h, lambda, (const float*)p, (float*)w, pcg_mode);
+    matvec_t<float>(h, lambda, (const float*)p, (float*)w, pcg_mode, pad_cams);
 }
 
 }  // namespace cba

@@ -104,11 +104,8 @@ __global__ void k_bj_points(int np, const double* __restrict__ Hpp, const S* __r
 
 // z = M^-1 r for block b (camera if b < nc, else point b - nc).
 template <typename S, int n>
-__device__ inline void block_apply(const S* __restrict__ Minv, const S* __restrict__ r, S* __restrict__ z,
-                                   double& rz, double& rr) {
-  S rv[n];
-#pragma unroll
-  for (int k = 0; k < n; ++k) rv[k] = r[k];
+__device__ inline void block_apply(const S* __restrict__ Minv, const S* rv, S* __restrict__ z, double& rz,
+                                   double& rr) {
   S mv[n * (n + 1) / 2];
 #pragma unroll
   for (int k = 0; k < n * (n + 1) / 2; ++k) mv[k] = Minv[k];
@@ -202,6 +199,29 @@ __global__ void k_pcg_scalar0(int n, const double* __restrict__ partials, double
 }
 
 // x += alpha p; r -= alpha w; z = M^-1 r; partials: r^T r, r^T z.
+// Stop test and beta after an update, from |r|^2 (a) and r^T z (c).
+__device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double c) {
+  sc->rr = a;
+  if (!isfinite(a) || !isfinite(c)) {
+    sc->done = 1;
+    sc->reason = PCG_BREAKDOWN;
+  } else if (a <= sc->tol2) {
+    sc->done = 1;
+    sc->reason = PCG_CONVERGED;
+  } else {
+    sc->beta = c / sc->rho;
+    sc->rho = c;
+    if (sc->iter >= sc->max_iter) {
+      sc->done = 1;
+      sc->reason = PCG_MAXITER;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha w, z = M^-1 r, and the sums r^T r, r^T z.  Thread
+// i takes camera block i and point block i (grid-stride), each with its
+// whole block in registers (vector loads of 3 or 9 consecutive values).
+// Workgroup sums go to the partial slots.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __restrict__ Mc,
                                                     const S* __restrict__ Mp, S* __restrict__ x,
@@ -213,29 +233,61 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
   if (sc->done) return;
   const double alpha = sc->alpha;
   double rz = 0.0, rr = 0.0;
-  const int64_t nb = (int64_t)nc + np;
-  for (int64_t blk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; blk < nb;
-       blk += (int64_t)gridDim.x * blockDim.x) {
-    const bool cam = blk < nc;
-    const int n = cam ? 9 : 3;
-    const size_t o = cam ? 9 * (size_t)blk : 9 * (size_t)nc + 3 * (size_t)(blk - nc);
-    for (int k = 0; k < n; ++k) {
-      x[o + k] = (S)fma(alpha, (double)p[o + k], (double)x[o + k]);
-      r[o + k] = (S)fma(-alpha, (double)w[o + k], (double)r[o + k]);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t c = i0; c < nc; c += stride) {
+    const size_t o = 9 * (size_t)c;
+    S pv[9], wv[9], xv[9], rv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      pv[k] = p[o + k];
+      wv[k] = w[o + k];
+      xv[k] = x[o + k];
+      rv[k] = r[o + k];
     }
-    if (cam)
-      block_apply<S, 9>(Mc + 45 * blk, r + o, z + o, rz, rr);
-    else
-      block_apply<S, 3>(Mp + 6 * (blk - nc), r + o, z + o, rz, rr);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      x[o + k] = (S)fma(alpha, (double)pv[k], (double)xv[k]);
+      rv[k] = (S)fma(-alpha, (double)wv[k], (double)rv[k]);
+      r[o + k] = rv[k];
+    }
+    block_apply<S, 9>(Mc + 45 * c, rv, z + o, rz, rr);
   }
-  const double a = block_sum(rr, red);
-  const double c = block_sum(rz, red);
+  const S* __restrict__ pp = p + 9 * (size_t)nc;
+  const S* __restrict__ wp = w + 9 * (size_t)nc;
+  S* __restrict__ xp = x + 9 * (size_t)nc;
+  S* __restrict__ rp = r + 9 * (size_t)nc;
+  S* __restrict__ zp = z + 9 * (size_t)nc;
+  for (int64_t i = i0; i < np; i += stride) {
+    const size_t o = 3 * (size_t)i;
+    S pv[3], wv[3], xv[3], rv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      pv[k] = pp[o + k];
+      wv[k] = wp[o + k];
+      xv[k] = xp[o + k];
+      rv[k] = rp[o + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xp[o + k] = (S)fma(alpha, (double)pv[k], (double)xv[k]);
+      rv[k] = (S)fma(-alpha, (double)wv[k], (double)rv[k]);
+      rp[o + k] = rv[k];
+    }
+    block_apply<S, 3>(Mp + 6 * i, rv, zp + o, rz, rr);
+  }
+  const double sa = block_sum(rr, red);
+  const double sz = block_sum(rz, red);
   if (threadIdx.x == 0) {
-    partials[(size_t)blockIdx.x * kPartialWidth] = a;
-    partials[(size_t)blockIdx.x * kPartialWidth + 1] = c;
+    partials[(size_t)blockIdx.x * kPartialWidth] = sa;
+    partials[(size_t)blockIdx.x * kPartialWidth + 1] = sz;
   }
 }
 
+// Sums the update's partials in slot order (deterministic) and sets the PCG
+// scalars.  A separate single-workgroup launch: folding this into the
+// update's last workgroup needs a device-scope fence per workgroup, which
+// writes back the L2 of its XCD and costs more than the launch.
 __global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevScalars* sc) {
   __shared__ double red[16];
   if (sc->done) return;
@@ -246,33 +298,44 @@ __global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevSca
   }
   a = block_sum(a, red);
   c = block_sum(c, red);
-  if (threadIdx.x == 0) {
-    sc->rr = a;
-    if (!isfinite(a) || !isfinite(c)) {
-      sc->done = 1;
-      sc->reason = PCG_BREAKDOWN;
-    } else if (a <= sc->tol2) {
-      sc->done = 1;
-      sc->reason = PCG_CONVERGED;
-    } else {
-      sc->beta = c / sc->rho;
-      sc->rho = c;
-      if (sc->iter >= sc->max_iter) {
-        sc->done = 1;
-        sc->reason = PCG_MAXITER;
-      }
-    }
-  }
+  if (threadIdx.x == 0) pcg_scalars_after_update(sc, a, c);
 }
 
-// p = z + beta p.
+// p = z + beta p, four elements per thread with 16-byte vector accesses;
+// the camera part is also written to the padded camera rows that the next
+// product gathers from.
 template <typename S>
-__global__ __launch_bounds__(256) void k_pcg_p(int64_t N, const S* __restrict__ z, S* __restrict__ p,
-                                               const DevScalars* __restrict__ sc) {
+__global__ __launch_bounds__(256) void k_pcg_p(int64_t N, int nc, const S* __restrict__ z, S* __restrict__ p,
+                                               S* __restrict__ p_cam, const DevScalars* __restrict__ sc) {
+  using V = S __attribute__((ext_vector_type(4)));
   if (sc->done) return;
   const double beta = sc->beta;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = (S)fma(beta, (double)p[i], (double)z[i]);
+  const int64_t ncam = 9 * (int64_t)nc;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  auto to_row = [&](int64_t e, S v) {
+    if (e < ncam) p_cam[(e / 9) * CamPad<S>::n + e % 9] = v;
+  };
+  const int64_t n4 = N / 4;
+  const V* __restrict__ z4 = reinterpret_cast<const V*>(z);
+  V* __restrict__ p4 = reinterpret_cast<V*>(p);
+  for (int64_t q = i0; q < n4; q += stride) {
+    const V zv = z4[q];
+    const V pv = p4[q];
+    V o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (S)fma(beta, (double)pv[k], (double)zv[k]);
+    p4[q] = o;
+    if (4 * q < ncam) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) to_row(4 * q + k, o[k]);
+    }
+  }
+  for (int64_t e = 4 * n4 + i0; e < N; e += stride) {
+    const S o = (S)fma(beta, (double)p[e], (double)z[e]);
+    p[e] = o;
+    to_row(e, o);
+  }
 }
 
 // Partials of sum a b and (if e) sum a e b.
@@ -400,18 +463,22 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
   CBA_LAUNCHED();
   k_pcg_scalar0<<<1, 1024, 0, st>>>((int)vg, h->partials, tol, max_iters, h->scal);
   CBA_LAUNCHED();
-  const unsigned pg = vec_grid(std::max<int64_t>(N, 1));
+  const unsigned ug = (unsigned)std::min<int64_t>(nblk(std::max<int64_t>(std::max(h->nc, h->np), 1), 256),
+                                                  kMaxPartials);
+  const unsigned pg = (unsigned)std::min<int64_t>(nblk(std::max<int64_t>(N / 4, 1), 256), 4096);
   check_every = std::max(1, check_every);
   DevScalars s = read_scalars(h);
   int launched = 0;
   while (!s.done && launched <= max_iters) {
     for (int k = 0; k < check_every; ++k) {
-      run_matvec(h, lambda, p, w, true);
-      k_pcg_update<S><<<vg, 256, 0, st>>>(h->nc, h->np, Mc, Mp, x, r, z, p, w, h->scal, h->partials);
+      // the first product pads the camera rows of p itself; later ones use
+      // the rows written by k_pcg_p
+      run_matvec(h, lambda, p, w, true, launched + k == 0);
+      k_pcg_update<S><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, x, r, z, p, w, h->scal, h->partials);
       CBA_LAUNCHED();
-      k_pcg_scalar1<<<1, 1024, 0, st>>>((int)vg, h->partials, h->scal);
+      k_pcg_scalar1<<<1, 1024, 0, st>>>((int)ug, h->partials, h->scal);
       CBA_LAUNCHED();
-      k_pcg_p<S><<<pg, 256, 0, st>>>(N, z, p, h->scal);
+      k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, (S*)h->p_cam, h->scal);
       CBA_LAUNCHED();
     }
     launched += check_every;
