@@ -52,11 +52,13 @@ constexpr int kColdRow = 10;         // doubles per cold-camera row (9 sums, pad
 constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
 constexpr int kPrivCams = 16;        // most observed cameras with private LDS copies in the product
 constexpr int kPrivCopies = 4;
+constexpr int kColdWin = 128;        // cold cameras per product workgroup accumulated in its LDS window
 constexpr int kMaxHot = kLdsBudget / (9 * 8);  // 2048 cameras with float64 sums
 constexpr int kMaxPartials = 4096;   // per-workgroup partial slots
 constexpr int kPartialWidth = 4;     // doubles per partial slot
 constexpr int kCamBits = 25;         // meta: camera id bits; local point in bits 25..30
 constexpr int kNumCUs = 256;
+constexpr int kMaxGroups = 2 * kNumCUs;  // workgroups of the fused product, at most
 
 // Padded camera row of the fused product's input vector: 10 doubles (5 x 16 B)
 // or 12 floats (3 x 16 B).
@@ -140,7 +142,10 @@ struct caspar_ba {
   int G = 0;              // workgroups of the fused product
   int n_tiles = 0;
   int n_cold = 0;         // observations of cameras >= K
-  int n_cold_rows = 0;    // distinct (tile, camera >= K) pairs: rows of the fused product
+  int n_cold_rows = 0;    // rows of the fused product for cameras >= K: one per observation outside
+                          // its workgroup's window, then kColdWin per workgroup for the windows
+  int L = 0;              // cold cameras in each workgroup's LDS window
+  int cold_local_base = 0;  // first window row
   int n_split_tiles = 0;
   int n_split_pts = 0;
   int n_orphan_pts = 0;   // points without observations (internal ids [0, n_orphan))
@@ -177,11 +182,11 @@ struct caspar_ba {
   double* chunk_rows = nullptr; // [n_chunks][54]
 
   // fused product side buffers
-  uint8_t* cold_perm = nullptr; // [n_tiles][64] lanes of a tile's cold observations sorted by camera
+  int* cold_lo = nullptr;       // [G] first camera of each product workgroup's LDS window
   void* p_cam = nullptr;        // [nc][kCamPad] camera part of the product's input, 16-byte rows
   int* cold_list = nullptr;     // cold rows grouped by camera
   int* cold_off = nullptr;      // [nc - K + 1]
-  void* cold_rows = nullptr;    // [n_cold][9] accumulator type
+  void* cold_rows = nullptr;    // [n_cold_rows][kColdRow] float64
   cba::SplitPoint* split_pts = nullptr;
   double* split_rows = nullptr; // [n_split_tiles][9]
   void* hot_rows = nullptr;     // [G][K][9] accumulator type
@@ -220,7 +225,7 @@ struct Plan {
     size_t off = 0, bytes = 0;
   };
   Region cam, cam_trial, cam_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
-      tiles, cold_perm, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
+      tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
@@ -233,6 +238,14 @@ inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
 // The fused product accumulates camera sums in float64 in both precisions
 // (ds_add_f64 in LDS measured faster than ds_add_f32 on this chip).
 inline size_t acc_bytes(int) { return 8; }
+
+// LDS of one fused-product workgroup: float64 sums of the K hot cameras,
+// kPrivCopies private copies of the most observed ones, and the L cameras of
+// the workgroup's cold window.
+inline size_t matvec_lds_bytes(int K, int L) {
+  const int P = K < kPrivCams ? K : kPrivCams;
+  return ((size_t)K + (size_t)kPrivCopies * P + (size_t)L) * 9 * sizeof(double);
+}
 
 // Launch helpers implemented per translation unit (S = double or float).
 // layout.hip

@@ -55,10 +55,7 @@ static size_t sort_temp_bytes(int64_t no) {
   return std::max(a, b) + (1 << 20);
 }
 
-static int groups_per_cu(int K, int prec) {
-  const size_t lds = (size_t)K * 9 * acc_bytes(prec);
-  return lds > 80 * 1024 ? 1 : 2;
-}
+static int groups_per_cu(int K, int L) { return matvec_lds_bytes(K, L) > 80 * 1024 ? 1 : 2; }
 
 bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   if (nc < 0 || np < 0 || no < 0) return false;
@@ -76,7 +73,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   const size_t N = 9 * (size_t)nc + 3 * (size_t)np;
   p = Plan{};
   p.K = std::min(nc, kMaxHot);
-  p.G = groups_per_cu(p.K, prec) * kNumCUs;
+  p.G = groups_per_cu(p.K, std::min(kColdWin, nc - p.K)) * kNumCUs;
   p.max_tiles = (size_t)no / 16 + 8;
   p.max_chunks = (size_t)no / kCamChunk + nc + 1;
   p.max_cold = nc > p.K ? (size_t)((no * (int64_t)(nc - p.K)) / nc + 1) : 0;
@@ -109,7 +106,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
                          align_up(sort_bytes) + 8 * (size_t)np + 8 * (size_t)nc + 8192;
   take(p.J, std::max(rj ? 0 : nch * no_pad * 16, scratch));
   take(p.tiles, p.max_tiles * sizeof(Tile));
-  take(p.cold_perm, nc > p.K ? p.max_tiles * 64 : 64);
+  take(p.cold_lo, (size_t)kMaxGroups * 4);
   take(p.p_cam, (size_t)nc * 80);  // 10 doubles or 12 floats per camera
   take(p.cm_pt, (size_t)no * 4);
   take(p.cm_px, (size_t)no * 16);
@@ -117,9 +114,10 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.chunks, p.max_chunks * sizeof(Chunk));
   take(p.chunk_off, ((size_t)nc + 1) * 4);
   take(p.chunk_rows, p.max_chunks * kCamRowWidth * 8);
-  take(p.cold_list, p.max_cold * 4 + 4);
+  const size_t max_cold_rows = nc > p.K ? p.max_cold + (size_t)kMaxGroups * kColdWin : 0;
+  take(p.cold_list, max_cold_rows * 4 + 4);
   take(p.cold_off, ((size_t)(nc - p.K) + 1) * 4);
-  take(p.cold_rows, p.max_cold * kColdRow * 8 + 16);
+  take(p.cold_rows, max_cold_rows * kColdRow * 8 + 16);
   take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
   take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
   take(p.hot_rows, (size_t)p.G * p.K * 9 * acc_bytes(prec));
@@ -511,53 +509,83 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   h2d(h, h->chunk_off, chunk_off);
   h2d(h, h->chunks, chunks);
 
-  // Cold cameras (internal id >= K): inside each tile the observations of
-  // one cold camera share a row of the fused product.  Per tile: the lanes of
-  // its cold observations sorted by camera (then lane), and one row per
-  // distinct cold camera, numbered in that order.  Per camera: its rows.
+  // Fused-product grid: workgroup g takes tiles [n_tiles g / G, n_tiles (g + 1) / G).
+  const int waves = matvec_waves(h->prec, h->rj);
+  h->L = nc > h->K ? std::min(kColdWin, nc - h->K) : 0;
+  h->G = std::max(1, std::min(groups_per_cu(h->K, h->L) * kNumCUs, (h->n_tiles + waves - 1) / waves));
+
+  // Cold cameras (internal id >= K).  Points are ordered by their least
+  // observed camera, so the cold observations of one workgroup's tiles
+  // concentrate on a narrow band of camera ids: each workgroup gets the
+  // window of L consecutive cold cameras holding most of its cold
+  // observations and sums them in LDS (rows local_base + g L + slot).  Every
+  // other cold observation writes a row of its own: per tile, rows
+  // cold_begin, cold_begin + 1, ... in lane order.  Per camera: its rows.
   h->n_cold = (nc > h->K) ? cam_off[nc] - cam_off[h->K] : 0;
   h->n_cold_rows = 0;
+  h->cold_local_base = 0;
   if (h->n_cold > 0) {
     std::vector<uint32_t> meta_h = d2h(h, h->meta, (size_t)no);
-    std::vector<uint8_t> perm((size_t)h->n_tiles * 64, 0);
-    std::vector<std::vector<int>> rows_of(nc - h->K);
-    std::vector<std::pair<int, int>> cl;
+    const int K = h->K, L = h->L, G = h->G;
+    auto cam_of = [&](int t, int lane) { return (int)(meta_h[tiles[t].obs_begin + lane] & ((1u << kCamBits) - 1)); };
+    std::vector<int> lo(G, K);
+    std::vector<std::vector<int>> rows_of(nc - K);
+    std::vector<int> ids;
     int run = 0, n_cold_seen = 0;
-    for (int t = 0; t < h->n_tiles; ++t) {
-      const int n = tile_nobs(tiles[t].info);
-      cl.clear();
-      for (int lane = 0; lane < n; ++lane) {
-        const int ci = (int)(meta_h[tiles[t].obs_begin + lane] & ((1u << kCamBits) - 1));
-        if (ci >= h->K) cl.emplace_back(ci, lane);
+    for (int g = 0; g < G; ++g) {
+      const int t0 = (int)((int64_t)h->n_tiles * g / G), t1 = (int)((int64_t)h->n_tiles * (g + 1) / G);
+      ids.clear();
+      for (int t = t0; t < t1; ++t)
+        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane)
+          if (cam_of(t, lane) >= K) ids.push_back(cam_of(t, lane));
+      std::sort(ids.begin(), ids.end());
+      // window [lo, lo + L) holding the most of this workgroup's cold observations
+      int best = 0;
+      for (size_t i = 0, j = 0; i < ids.size(); ++i) {
+        while (j < ids.size() && ids[j] < ids[i] + L) ++j;
+        if ((int)(j - i) > best) {
+          best = (int)(j - i);
+          lo[g] = std::min(ids[i], nc - L);
+        }
       }
-      std::sort(cl.begin(), cl.end());
-      tiles[t].cold_begin = run;
-      for (size_t j = 0; j < cl.size(); ++j) {
-        perm[(size_t)t * 64 + j] = (uint8_t)cl[j].second;
-        if (j == 0 || cl[j].first != cl[j - 1].first) rows_of[cl[j].first - h->K].push_back(run++);
+      for (int t = t0; t < t1; ++t) {
+        tiles[t].cold_begin = run;
+        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane) {
+          const int c = cam_of(t, lane);
+          if (c < K) continue;
+          ++n_cold_seen;
+          if (c < lo[g] || c >= lo[g] + L) rows_of[c - K].push_back(run++);
+        }
       }
-      n_cold_seen += (int)cl.size();
     }
     if (n_cold_seen != h->n_cold) fail(CASPAR_EINVAL, "internal: cold count mismatch");
-    if ((size_t)run > plan.max_cold) fail(CASPAR_ENOMEM, "internal: cold rows exceed plan");
-    h->n_cold_rows = run;
-    std::vector<int> coff(nc - h->K + 1, 0), clist;
-    clist.reserve(run);
-    for (int c = h->K; c < nc; ++c) {
-      coff[c - h->K + 1] = coff[c - h->K] + (int)rows_of[c - h->K].size();
-      clist.insert(clist.end(), rows_of[c - h->K].begin(), rows_of[c - h->K].end());
+    if ((size_t)run > plan.max_cold || G > kMaxGroups) fail(CASPAR_ENOMEM, "internal: cold rows exceed plan");
+    // window rows, listed for the cameras that have observations in them
+    h->cold_local_base = run;
+    for (int g = 0; g < G; ++g) {
+      std::vector<char> used(L, 0);
+      const int t0 = (int)((int64_t)h->n_tiles * g / G), t1 = (int)((int64_t)h->n_tiles * (g + 1) / G);
+      for (int t = t0; t < t1; ++t)
+        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane) {
+          const int c = cam_of(t, lane);
+          if (c >= K && c >= lo[g] && c < lo[g] + L) used[c - lo[g]] = 1;
+        }
+      for (int sl = 0; sl < L; ++sl)
+        if (used[sl]) rows_of[lo[g] + sl - K].push_back(run + g * L + sl);
+    }
+    h->n_cold_rows = run + G * L;
+    std::vector<int> coff(nc - K + 1, 0), clist;
+    for (int c = K; c < nc; ++c) {
+      coff[c - K + 1] = coff[c - K] + (int)rows_of[c - K].size();
+      clist.insert(clist.end(), rows_of[c - K].begin(), rows_of[c - K].end());
     }
     h2d(h, h->tiles, tiles);
-    h2d(h, h->cold_perm, perm);
+    h2d(h, h->cold_lo, lo);
     h2d(h, h->cold_off, coff);
     h2d(h, h->cold_list, clist);
   } else if (no) {
     h2d(h, h->tiles, tiles);
   }
-
-  // Fused-product grid.
-  const int waves = matvec_waves(h->prec, h->rj);
-  h->G = std::max(1, std::min(groups_per_cu(h->K, h->prec) * kNumCUs, (h->n_tiles + waves - 1) / waves));
 
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);
@@ -659,7 +687,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->px = (double*)(ws + plan.px.off);
     h->J = ws + plan.J.off;
     h->tiles = (Tile*)(ws + plan.tiles.off);
-    h->cold_perm = (uint8_t*)(ws + plan.cold_perm.off);
+    h->cold_lo = (int*)(ws + plan.cold_lo.off);
     h->p_cam = ws + plan.p_cam.off;
     h->cm_obs = (int*)(ws + plan.cm_obs.off);
     h->cm_pt = (int*)(ws + plan.cm_pt.off);

@@ -70,7 +70,8 @@ __device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c
 //                 camera gathers of the tile itself);
 //   prefetch_cam: the camera rows of p and, with recomputed blocks, the
 //                 camera parameters and the point (otherwise gathered at the
-//                 start of the tile, with their latency exposed).
+//                 start of the tile, with their latency exposed; float64
+//                 stored blocks would spill).
 template <typename S, bool RJ>
 struct MvCfg {
   static constexpr int threads = 1024;
@@ -82,7 +83,7 @@ template <>
 struct MvCfg<double, false> {
   static constexpr int threads = 1024;
   static constexpr bool prefetch_j = false;
-  static constexpr bool prefetch_pt = false;
+  static constexpr bool prefetch_pt = true;
   static constexpr bool prefetch_cam = false;
 };
 template <>
@@ -112,10 +113,10 @@ template <typename S, bool RJ>
 __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
     const void* __restrict__ J, const S* __restrict__ cam_s, const double* __restrict__ Xpts,
-    const S* __restrict__ p_cam, const uint8_t* __restrict__ cold_perm,
+    const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
-    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P) {
+    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base) {
   constexpr int THREADS = MvCfg<S, RJ>::threads;
   constexpr int WAVES = THREADS / kWave;
   constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
@@ -127,12 +128,15 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   // mod kPrivCopies), so lanes of one wave hitting the same camera mostly
   // update different addresses; folded into hot[] before the flush
   double* priv = hot + (size_t)K * 9;                      // [kPrivCopies][P][9]
+  // this workgroup's window of cold cameras [lo, lo + L)
+  double* win = priv + (size_t)kPrivCopies * P * 9;        // [L][9]
+  const int lo = L > 0 ? cold_lo[blockIdx.x] : 0;
   __shared__ double red[WAVES];
   if (sc != nullptr && sc->done) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  for (int i = tid; i < (K + kPrivCopies * P) * 9; i += THREADS) hot[i] = 0.0;
+  for (int i = tid; i < (K + kPrivCopies * P + L) * 9; i += THREADS) hot[i] = 0.0;
   __syncthreads();
 
   const S* __restrict__ pp_base = p + 9 * (size_t)nc;
@@ -145,11 +149,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   // Software pipeline over the wave's tiles t, t + W, t + 2W, t + 3W (W =
   // waves per workgroup):
   //   tile t       being computed: meta word, Jacobian columns, p and D of
-  //                its points, the camera rows of p and the cold permutation
-  //                are in registers (whatever the configuration does not
-  //                prefetch is gathered at the start of the tile);
-  //   tile t + W   meta in registers; its Jacobian columns, point data,
-  //                camera rows and permutation are requested during tile t;
+  //                its points and the camera rows of p are in registers
+  //                (whatever the configuration does not prefetch is
+  //                gathered at the start of the tile);
+  //   tile t + W   meta in registers; its Jacobian columns, point data and
+  //                camera rows are requested during tile t;
   //   tile t + 2W  meta requested during tile t;
   //   tile t + 3W  descriptor requested during tile t.
   // The tile index is wave-uniform, so descriptors come through the scalar
@@ -157,15 +161,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   // end, and tiles past the range, read clamped in-range addresses and
   // their values are unused), so each iteration issues a fixed number of
   // loads and every wait covers exactly the loads it needs.
-  const bool has_cold = nc > K;
   int t = t0 + __builtin_amdgcn_readfirstlane(wv);
   if (t < t1) {
     auto nobs = [&](int ti, const Tile& T) { return ti < t1 ? tile_nobs(T.info) : 0; };
     auto olane = [&](int k) { return min(lane, max(k, 1) - 1); };
     auto tile_at = [&](int ti) { return tiles[min(ti, t1 - 1)]; };
-    auto perm_at = [&](int ti) {
-      return (int)cold_perm[has_cold ? (size_t)min(ti, t1 - 1) * kWave + lane : (size_t)lane];
-    };
     Tile tl = tiles[t], tln = tile_at(t + WAVES), tlnn = tile_at(t + 2 * WAVES);
     int n = tile_nobs(tl.info);
     uint32_t m = meta[tl.obs_begin + olane(n)];
@@ -193,7 +193,6 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
         for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
       }
     }
-    int perm = perm_at(t);
     for (;;) {
       const bool act = lane < n;
       const int ci_raw = (int)(m & ((1u << kCamBits) - 1));
@@ -247,7 +246,6 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
           for (int k = 0; k < 3; ++k) xjn[k] = Xp[k];
         }
       }
-      const int permn = perm_at(tn);
       const uint32_t mnn = meta[tlnn.obs_begin + olane(nobs(tn + WAVES, tlnn))];
       const Tile tl3 = tile_at(tn + 2 * WAVES);
       __builtin_amdgcn_sched_barrier(0);
@@ -278,44 +276,26 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
         for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
 #pragma unroll
         for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
-        if (ci < K) {
-          double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9 : hot + 9 * ci;
+        // LDS sums: the most observed cameras into their private copies,
+        // the other hot cameras, and the cold cameras of this workgroup's
+        // window
+        const unsigned slot = (unsigned)(ci - lo);
+        if (ci < K || slot < (unsigned)L) {
+          double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9
+                             : (ci < K ? hot + 9 * ci : win + 9 * slot);
 #pragma unroll
           for (int k = 0; k < 9; ++k) atomicAdd(a + k, (double)yc[k]);
         }
       }
-      // cameras outside the LDS set: the tile's cold lanes, gathered in camera
-      // order, sum runs of one camera; each run's first lane writes its row
-      const bool cold = act && ci >= K;
-      const unsigned long long cm = __ballot(cold);
-      if (cm != 0ull) {
-        const int ncold = __popcll(cm);
-        const bool valid = lane < ncold;
-        const int src = valid ? perm : lane;
-        int key = __shfl(ci, src, kWave);
-        key = valid ? key : -1 - lane;
-        S v[9];
+      // cold cameras outside the window: each such observation writes its
+      // own row, numbered from the tile's cold_begin in lane order
+      const bool scat = act && ci >= K && (unsigned)(ci - lo) >= (unsigned)L;
+      const unsigned long long sm = __ballot(scat);
+      if (scat) {
+        double vd[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = __shfl(yc[k], src, kWave);
-        for (int d = 1; d < kWave; d <<= 1) {
-          const int okey = __shfl_down(key, d, kWave);
-          const bool take = (lane + d < kWave) && okey == key;
-          if (!__any(take)) break;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            const S o = __shfl_down(v[k], d, kWave);
-            if (take) v[k] += o;
-          }
-        }
-        const int pkey = __shfl_up(key, 1, kWave);
-        const bool head = valid && (lane == 0 || pkey != key);
-        const unsigned long long hm = __ballot(head);
-        if (head) {
-          double vd[9];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) vd[k] = (double)v[k];
-          store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(hm & ((1ull << lane) - 1ull))) * kColdRow, vd);
-        }
+        for (int k = 0; k < 9; ++k) vd[k] = (double)yc[k];
+        store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(sm & ((1ull << lane) - 1ull))) * kColdRow, vd);
       }
       // points: segmented suffix sums, the first lane of each point holds the total
       const int steps = tile_steps(tl.info);
@@ -357,7 +337,6 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       tl = tln;
       n = nobs(t, tl);
       m = mn;
-      perm = permn;
       tln = tlnn;
       mn = mnn;
       tlnn = tl3;
@@ -410,6 +389,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   __syncthreads();
   double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
   for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
+  double* wdst = cold_rows + ((size_t)local_base + (size_t)blockIdx.x * L) * kColdRow;
+  for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
 }
 
 // Camera rows of w, split and orphan points, p^T A p and (in PCG) alpha.
@@ -506,15 +487,15 @@ template <typename S, bool RJ>
 static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const DevScalars* scp) {
   constexpr int T = MvCfg<S, RJ>::threads;
   const int P = std::min(h->K, kPrivCams);
-  const size_t lds = ((size_t)h->K + (size_t)kPrivCopies * P) * 9 * sizeof(double);
+  const size_t lds = matvec_lds_bytes(h->K, h->L);
   auto kern = k_matvec<S, RJ>;
   if (lds > 65536)
     CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   timing_mark_start(h);
   kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, h->X,
-                                     (const S*)h->p_cam, h->cold_perm, p, (const S*)h->vec.D, lambda, w, h->nc,
+                                     (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
                                      h->K, h->n_orphan_pts, (double*)h->hot_rows, (double*)h->cold_rows,
-                                     h->split_rows, h->partials, scp, P);
+                                     h->split_rows, h->partials, scp, P, h->L, h->cold_local_base);
   CBA_LAUNCHED();
   timing_mark_stop(h);
 }
