@@ -117,7 +117,8 @@ typedef struct caspar_iter_record {
 CASPAR_API void caspar_default_solve_opts(caspar_solve_opts* opts);
 
 /* Bytes of device workspace a handle of this size needs (0 on bad sizes).
- * n_obs must be < 2^31, n_cams < 2^25.  mode = precision | Jacobian flag. */
+ * n_obs must be < 2^31, n_cams < 2^25 and 3 n_points scalars (float64 or
+ * float32 by precision) under 2 GiB.  mode = precision | Jacobian flag. */
 CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int mode);
 
 /* Build a problem (paper Sec. VI-A: cameras, points, observations).

@@ -64,6 +64,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   const int prec = mode & 1;
   const bool rj = (mode & CASPAR_RECOMPUTE_JACOBIAN) != 0;
   if (no > 0 && (nc == 0 || np == 0)) return false;
+  if (3 * (size_t)np * scalar_bytes(mode & 1) >= ((size_t)1 << 31)) return false;  // product's point rows
   if ((int64_t)9 * nc + 3 * (int64_t)np >= ((int64_t)1 << 31)) return false;
   const size_t s = scalar_bytes(prec);
   const size_t nch = prec == CASPAR_FP64 ? 12 : 6;
@@ -574,6 +575,8 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
         if (used[sl]) rows_of[lo[g] + sl - K].push_back(run + g * L + sl);
     }
     h->n_cold_rows = run + G * L;
+    if ((size_t)h->n_cold_rows * kColdRow * sizeof(double) >= ((size_t)1 << 31))
+      fail(CASPAR_EINVAL, "too many observations of rarely observed cameras: the product's row buffer exceeds 2 GiB");
     std::vector<int> coff(nc - K + 1, 0), clist;
     for (int c = K; c < nc; ++c) {
       coff[c - K + 1] = coff[c - K] + (int)rows_of[c - K].size();

@@ -99,14 +99,40 @@ int matvec_waves(int prec, bool rj) {
   return (rj ? MvCfg<float, true>::threads : MvCfg<float, false>::threads) / kWave;
 }
 
-// Writes one cold row (9 sums, padded to kColdRow doubles: five 16-byte stores).
-__device__ inline void store_cold_row(double* row, const double v[9]) {
-  double2* r = reinterpret_cast<double2*>(row);
-  r[0] = make_double2(v[0], v[1]);
-  r[1] = make_double2(v[2], v[3]);
-  r[2] = make_double2(v[4], v[5]);
-  r[3] = make_double2(v[6], v[7]);
-  r[4] = make_double2(v[8], 0.0);
+// Stores that only some lanes need are issued by every lane through a buffer
+// resource: a lane with nothing to write passes an offset past the end of
+// the buffer and the hardware drops its write.  Each loop iteration then
+// issues the same memory operations on every path, so the compiler's wait
+// counts stay exact and no load waits for a store issued after it.
+constexpr unsigned kDropOffset = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+using u32x4 = unsigned __attribute__((ext_vector_type(4)));
+using u32x3 = unsigned __attribute__((ext_vector_type(3)));
+using u32x2 = unsigned __attribute__((ext_vector_type(2)));
+
+// One cold row at byte offset off: 9 float64 sums padded to kColdRow (five
+// 16-byte stores).
+__device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, const double v[9]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double2 d = make_double2(v[2 * i], i < 4 ? v[2 * i + 1] : 0.0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, d), rs, (int)off + 16 * i, 0, 0);
+  }
+}
+
+// Three consecutive scalars at byte offset off.
+__device__ inline void store3(__amdgpu_buffer_rsrc_t rs, unsigned off, const float v[3]) {
+  const u32x3 u = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
+  __builtin_amdgcn_raw_buffer_store_b96(u, rs, (int)off, 0, 0);
+}
+__device__ inline void store3(__amdgpu_buffer_rsrc_t rs, unsigned off, const double v[3]) {
+  const double2 d = make_double2(v[0], v[1]);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, d), rs, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[2]), rs, (int)off + 16, 0, 0);
 }
 
 template <typename S, bool RJ>
@@ -116,7 +142,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
-    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base) {
+    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base,
+    unsigned w_pt_bytes, unsigned cold_bytes) {
   constexpr int THREADS = MvCfg<S, RJ>::threads;
   constexpr int WAVES = THREADS / kWave;
   constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
@@ -142,6 +169,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   const S* __restrict__ pp_base = p + 9 * (size_t)nc;
   const S* __restrict__ dp_base = D + 9 * (size_t)nc;
   S* __restrict__ wp_base = w + 9 * (size_t)nc;
+  const __amdgpu_buffer_rsrc_t w_rs = buffer_of(wp_base, w_pt_bytes);
+  const __amdgpu_buffer_rsrc_t cold_rs = buffer_of(cold_rows, cold_bytes);
   double pap = 0.0;
   const int t0 = (int)((int64_t)n_tiles * blockIdx.x / G);
   const int t1 = (int)((int64_t)n_tiles * (blockIdx.x + 1) / G);
@@ -291,11 +320,12 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       // own row, numbered from the tile's cold_begin in lane order
       const bool scat = act && ci >= K && (unsigned)(ci - lo) >= (unsigned)L;
       const unsigned long long sm = __ballot(scat);
-      if (scat) {
+      {
         double vd[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) vd[k] = (double)yc[k];
-        store_cold_row(cold_rows + (size_t)(tl.cold_begin + __popcll(sm & ((1ull << lane) - 1ull))) * kColdRow, vd);
+        const unsigned row = (unsigned)tl.cold_begin + (unsigned)__popcll(sm & ((1ull << lane) - 1ull));
+        store_cold_row(cold_rs, scat ? row * (unsigned)(kColdRow * sizeof(double)) : kDropOffset, vd);
       }
       // points: segmented suffix sums, the first lane of each point holds the total
       const int steps = tile_steps(tl.info);
@@ -310,26 +340,25 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       }
       const int prev = __shfl_up(lp, 1, kWave);
       const bool head = act && (lane == 0 || prev != lp);
-      if (head) {
-        const size_t b = 3 * (size_t)(tl.pt_begin + lp);
-        if (tile_split(tl.info)) {
-          double* row = split_rows + (size_t)tl.split_row * kPtRowWidth;
+      const bool split = tile_split(tl.info);
+      // lambda p^T D p, once per point
+      if (head && (!split || tile_first(tl.info))) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) row[k] = (double)yp[k];
-          if (tile_first(tl.info)) {
+        for (int k = 0; k < 3; ++k) pap = fma(lambda * (double)dpv[k] * (double)pjv[k], (double)pjv[k], pap);
+      }
+      // the point rows of w (ordinary tiles)
+      {
+        S wv[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              const double v = pjv[k];
-              pap = fma(lambda * (double)dpv[k] * v, v, pap);
-            }
-          }
-        } else {
+        for (int k = 0; k < 3; ++k) wv[k] = fma((S)lambda * dpv[k], pjv[k], yp[k]);
+        const unsigned off = (unsigned)(3 * (tl.pt_begin + lp)) * (unsigned)sizeof(S);
+        store3(w_rs, head && !split ? off : kDropOffset, wv);
+      }
+      // a slice of a point with more than kTileMax observations: its row
+      if (split && head) {
+        double* row = split_rows + (size_t)tl.split_row * kPtRowWidth;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            wp_base[b + k] = fma((S)lambda * dpv[k], pjv[k], yp[k]);
-            pap = fma(lambda * (double)dpv[k] * (double)pjv[k], (double)pjv[k], pap);
-          }
-        }
+        for (int k = 0; k < 3; ++k) row[k] = (double)yp[k];
       }
       // 4. advance
       t = tn;
@@ -495,7 +524,9 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
   kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, h->X,
                                      (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
                                      h->K, h->n_orphan_pts, (double*)h->hot_rows, (double*)h->cold_rows,
-                                     h->split_rows, h->partials, scp, P, h->L, h->cold_local_base);
+                                     h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,
+                                     (unsigned)(3 * (size_t)h->np * sizeof(S)),
+                                     (unsigned)((size_t)h->n_cold_rows * kColdRow * sizeof(double)));
   CBA_LAUNCHED();
   timing_mark_stop(h);
 }
