@@ -9,11 +9,16 @@ accept/reject update.  W untimed iterations run first (from the initial
 values), then the parameters are reset and exactly K iterations are timed
 (early stopping off), with inputs resident in HBM.
 
+The headline recomputes the Jacobian blocks inside every normal-equation
+product (--jacobian recompute); the run with stored blocks follows it.
+
 Printed: one JSON line with LM iterations/s (value), the roofline of the
 fused product (its average duration measured with HIP events on the
-library's stream during the timed solve), the float64 plain solve beside the
-float32-mixed one with the cost error between them, the implicit-adjoint
-backward time, and the float64 CPU oracle timed on a bounded sample.
+library's stream during the timed solve: priced on flops when the blocks are
+recomputed, on HBM bytes when they are stored), the float64 plain solve
+beside the float32-mixed one with the cost error between them, the other
+Jacobian handling, the implicit-adjoint backward time, and the float64 CPU
+oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
@@ -30,6 +35,15 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+# Float32 / float64 vector FMA issue without packed math (this build does not
+# use packed float32): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic flops of the fused product per observation: evaluating the
+# 2x9 / 2x3 blocks from the camera and the point (P = R X + t, projection,
+# distortion, the 2x3 chain factor, J_p = B R, J_w = -J_p [X]x, the three
+# calibration columns: 113) when they are not stored, plus applying them
+# (q = J p, J_c^T q, J_p^T q, |q|^2 and the sums: 100).
+FLOPS_PER_OBS = {"recompute": 213.0, "stored": 100.0}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -42,7 +56,7 @@ def parse():
                     choices=["tiny", "medium", "bal1700", "large_zipf"])
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     ap.add_argument("--pcg-tol", type=float, default=1e-3, help="PCG relative tolerance (paper: 1e-3)")
-    ap.add_argument("--jacobian", default="stored", choices=["stored", "recompute"],
+    ap.add_argument("--jacobian", default="recompute", choices=["stored", "recompute"],
                     help="store the Jacobian blocks at linearisation or evaluate them in every product")
     ap.add_argument("--no-alt-jacobian", action="store_true",
                     help="skip the run with the other Jacobian handling beside the headline one")
@@ -169,7 +183,8 @@ def main():
     iters = st["lm_iters"]
     value = iters / dt
     mv_avg_ms = tim["matvec_ms"] / max(1, tim["matvec_launches"])
-    achieved = tim["matvec_bytes"] / (mv_avg_ms * 1e-3) / 1e9 if tim["matvec_launches"] else None
+    gbs = tim["matvec_bytes"] / (mv_avg_ms * 1e-3) / 1e9 if tim["matvec_launches"] else None
+    tflops = FLOPS_PER_OBS[a.jacobian] * sc.n_obs / (mv_avg_ms * 1e-3) / 1e12 if tim["matvec_launches"] else None
     f_primary = ba.cost_fp64()
 
     extra = {}
@@ -192,6 +207,7 @@ def main():
         alt = "recompute" if a.jacobian == "stored" else "stored"
         ba_alt, st_alt, dt_alt, tim_alt = timed_solve(prec, f"{a.precision}/{alt}", jacobian=alt)
         mv_alt = tim_alt["matvec_ms"] / max(1, tim_alt["matvec_launches"])
+        gbs_alt = tim_alt["matvec_bytes"] / (mv_alt * 1e-3) / 1e9
         extra[f"{alt}_jacobian"] = {
             "lm_iters_per_s": st_alt["lm_iters"] / dt_alt,
             "ms_per_step": 1e3 * dt_alt / max(1, st_alt["lm_iters"]),
@@ -199,6 +215,9 @@ def main():
             "pcg_iters_total": st_alt["pcg_iters_total"],
             "matvec_avg_ms": mv_alt,
             "matvec_algorithmic_bytes": tim_alt["matvec_bytes"],
+            "matvec_gbs": gbs_alt,
+            "matvec_hbm_frac": gbs_alt / HBM_PEAK_GBS,
+            "matvec_tflops": FLOPS_PER_OBS[alt] * sc.n_obs / (mv_alt * 1e-3) / 1e12,
         }
         del ba_alt
         torch.cuda.empty_cache()
@@ -212,6 +231,23 @@ def main():
         extra["adjoint"] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": ba.last_backward_iters,
                             "loss": "sum of squared optimal point coordinates", "grad_norm": float(g.norm())}
 
+    if a.jacobian == "stored":
+        # the blocks stream from HBM: priced on the bytes the product must move
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS if gbs else None}
+    else:
+        # the blocks are evaluated in every product: priced on its flops
+        roofline = {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tflops / ALU_PEAK_TFLOPS if tflops else None}
+    roofline.update({
+        "traffic": counter_traffic(a.workload, a.precision, a.jacobian),
+        "kernel": "k_matvec",
+        "avg_ms": mv_avg_ms,
+        "launches": tim["matvec_launches"],
+        "algorithmic_bytes_per_launch": tim["matvec_bytes"],
+        "algorithmic_flops_per_launch": FLOPS_PER_OBS[a.jacobian] * sc.n_obs,
+        "hbm_gbs": gbs,
+    })
     line = {
         "metric": "LM iterations/sec + PCG matvec HBM GB/s, FP32-mixed vs FP64 at stated cost error",
         "value": value,
@@ -234,18 +270,7 @@ def main():
             "final_cost_fp64_eval": f_primary,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": counter_traffic(a.workload, a.precision, a.jacobian),
-            "kernel": "k_matvec",
-            "avg_ms": mv_avg_ms,
-            "launches": tim["matvec_launches"],
-            "algorithmic_bytes_per_launch": tim["matvec_bytes"],
-        },
+        "roofline": roofline,
     }
     line.update(extra)
     if not a.no_cpu_baseline:

@@ -48,7 +48,7 @@ constexpr int kCamStride = 16;       // doubles per camera row: R(9) t(3) f k1 k
 constexpr int kCamChunk = 2048;      // camera-major entries per linearisation chunk
 constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
 constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
-constexpr int kColdRow = 10;         // doubles per cold-camera row (9 sums, padded to 80 bytes)
+constexpr int kColdRow = 10;         // doubles per cold-camera window row (9 sums, padded to 80 bytes)
 constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
 constexpr int kPrivCams = 16;        // most observed cameras with private LDS copies in the product
 constexpr int kPrivCopies = 4;
@@ -62,6 +62,19 @@ constexpr int kMaxGroups = 2 * kNumCUs;  // workgroups of the fused product, at 
 
 // Padded camera row of the fused product's input vector: 10 doubles (5 x 16 B)
 // or 12 floats (3 x 16 B).
+// Row of one cold observation outside its workgroup's window: its 9 camera
+// values in the working precision, padded to whole 16-byte stores.
+template <typename S>
+struct ColdRow;
+template <>
+struct ColdRow<double> {
+  static constexpr int n = 10;
+};
+template <>
+struct ColdRow<float> {
+  static constexpr int n = 12;
+};
+
 template <typename S>
 struct CamPad;
 template <>
@@ -143,7 +156,8 @@ struct caspar_ba {
   int n_tiles = 0;
   int n_cold = 0;         // observations of cameras >= K
   int n_cold_rows = 0;    // rows of the fused product for cameras >= K: one per observation outside
-                          // its workgroup's window, then kColdWin per workgroup for the windows
+                          // its workgroup's window (working precision), then L per workgroup for the
+                          // windows (float64, in win_rows)
   int L = 0;              // cold cameras in each workgroup's LDS window
   int cold_local_base = 0;  // first window row
   int n_split_tiles = 0;
@@ -186,7 +200,8 @@ struct caspar_ba {
   void* p_cam = nullptr;        // [nc][kCamPad] camera part of the product's input, 16-byte rows
   int* cold_list = nullptr;     // cold rows grouped by camera
   int* cold_off = nullptr;      // [nc - K + 1]
-  void* cold_rows = nullptr;    // [n_cold_rows][kColdRow] float64
+  void* cold_rows = nullptr;    // [cold_local_base][ColdRow<S>::n] rows of single cold observations
+  double* win_rows = nullptr;   // [G][L][kColdRow] window sums (float64), inside the cold_rows region
   cba::SplitPoint* split_pts = nullptr;
   double* split_rows = nullptr; // [n_split_tiles][9]
   void* hot_rows = nullptr;     // [G][K][9] accumulator type

@@ -118,7 +118,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   const size_t max_cold_rows = nc > p.K ? p.max_cold + (size_t)kMaxGroups * kColdWin : 0;
   take(p.cold_list, max_cold_rows * 4 + 4);
   take(p.cold_off, ((size_t)(nc - p.K) + 1) * 4);
-  take(p.cold_rows, max_cold_rows * kColdRow * 8 + 16);
+  take(p.cold_rows, max_cold_rows * kColdRow * 8 + 256);  // single-observation rows, then window rows
   take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
   take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
   take(p.hot_rows, (size_t)p.G * p.K * 9 * acc_bytes(prec));
@@ -575,8 +575,10 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
         if (used[sl]) rows_of[lo[g] + sl - K].push_back(run + g * L + sl);
     }
     h->n_cold_rows = run + G * L;
-    if ((size_t)h->n_cold_rows * kColdRow * sizeof(double) >= ((size_t)1 << 31))
+    const size_t scat_bytes = (size_t)run * (h->prec == CASPAR_FP64 ? ColdRow<double>::n * 8 : ColdRow<float>::n * 4);
+    if (scat_bytes >= ((size_t)1 << 31))
       fail(CASPAR_EINVAL, "too many observations of rarely observed cameras: the product's row buffer exceeds 2 GiB");
+    h->win_rows = reinterpret_cast<double*>(static_cast<char*>(h->cold_rows) + align_up(scat_bytes));
     std::vector<int> coff(nc - K + 1, 0), clist;
     for (int c = K; c < nc; ++c) {
       coff[c - K + 1] = coff[c - K] + (int)rows_of[c - K].size();

@@ -114,13 +114,22 @@ using u32x4 = unsigned __attribute__((ext_vector_type(4)));
 using u32x3 = unsigned __attribute__((ext_vector_type(3)));
 using u32x2 = unsigned __attribute__((ext_vector_type(2)));
 
-// One cold row at byte offset off: 9 float64 sums padded to kColdRow (five
-// 16-byte stores).
+// One cold row at byte offset off: 9 values padded to ColdRow<S>::n (five
+// 16-byte stores in float64, three in float32).
 __device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, const double v[9]) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     const double2 d = make_double2(v[2 * i], i < 4 ? v[2 * i + 1] : 0.0);
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, d), rs, (int)off + 16 * i, 0, 0);
+  }
+}
+
+__device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, const float v[9]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const u32x4 u = {__float_as_uint(v[4 * i]), __float_as_uint(4 * i + 1 < 9 ? v[4 * i + 1] : 0.f),
+                     __float_as_uint(4 * i + 2 < 9 ? v[4 * i + 2] : 0.f), __float_as_uint(4 * i + 3 < 9 ? v[4 * i + 3] : 0.f)};
+    __builtin_amdgcn_raw_buffer_store_b128(u, rs, (int)off + 16 * i, 0, 0);
   }
 }
 
@@ -141,7 +150,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     const void* __restrict__ J, const S* __restrict__ cam_s, const double* __restrict__ Xpts,
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
-    int n_orphan, double* __restrict__ hot_rows, double* __restrict__ cold_rows, double* __restrict__ split_rows,
+    int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
+    double* __restrict__ split_rows,
     double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base,
     unsigned w_pt_bytes, unsigned cold_bytes) {
   constexpr int THREADS = MvCfg<S, RJ>::threads;
@@ -321,11 +331,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       const bool scat = act && ci >= K && (unsigned)(ci - lo) >= (unsigned)L;
       const unsigned long long sm = __ballot(scat);
       {
-        double vd[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) vd[k] = (double)yc[k];
         const unsigned row = (unsigned)tl.cold_begin + (unsigned)__popcll(sm & ((1ull << lane) - 1ull));
-        store_cold_row(cold_rs, scat ? row * (unsigned)(kColdRow * sizeof(double)) : kDropOffset, vd);
+        store_cold_row(cold_rs, scat ? row * (unsigned)(ColdRow<S>::n * sizeof(S)) : kDropOffset, yc);
       }
       // points: segmented suffix sums, the first lane of each point holds the total
       const int steps = tile_steps(tl.info);
@@ -418,7 +425,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   __syncthreads();
   double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
   for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
-  double* wdst = cold_rows + ((size_t)local_base + (size_t)blockIdx.x * L) * kColdRow;
+  double* wdst = win_rows + (size_t)blockIdx.x * L * kColdRow;
   for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
 }
 
@@ -433,7 +440,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 template <typename S>
 __global__ __launch_bounds__(256) void k_matvec_final(
     int nc, int K, int G, const double* __restrict__ hot_rows,
-    const double* __restrict__ cold_rows, const int* __restrict__ cold_off,
+    const S* __restrict__ cold_rows, const double* __restrict__ win_rows, int local_base,
+    const int* __restrict__ cold_off,
     const int* __restrict__ cold_list, const S* __restrict__ p, const S* __restrict__ D, double lambda,
     S* __restrict__ w, int n_split, const SplitPoint* __restrict__ sp, const double* __restrict__ split_rows,
     int n_orphan, const double* __restrict__ partials, DevScalars* __restrict__ sc, int pcg_mode, int nb_hot,
@@ -465,9 +473,16 @@ __global__ __launch_bounds__(256) void k_matvec_final(
 #pragma unroll
       for (int k = 0; k < 9; ++k) acc[k] = 0.0;
       for (int q = q0 + lane; q < q1; q += 64) {
-        const A* row = cold_rows + (size_t)cold_list[q] * kColdRow;
+        const int e = cold_list[q];
+        if (e < local_base) {
+          const S* row = cold_rows + (size_t)e * ColdRow<S>::n;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += (double)row[k];
+          for (int k = 0; k < 9; ++k) acc[k] += (double)row[k];
+        } else {
+          const double* row = win_rows + (size_t)(e - local_base) * kColdRow;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) acc[k] += row[k];
+        }
       }
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
@@ -523,10 +538,10 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
   timing_mark_start(h);
   kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, h->X,
                                      (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
-                                     h->K, h->n_orphan_pts, (double*)h->hot_rows, (double*)h->cold_rows,
+                                     h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows, h->win_rows,
                                      h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,
                                      (unsigned)(3 * (size_t)h->np * sizeof(S)),
-                                     (unsigned)((size_t)h->n_cold_rows * kColdRow * sizeof(double)));
+                                     (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)));
   CBA_LAUNCHED();
   timing_mark_stop(h);
 }
@@ -551,7 +566,8 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   const int nb_rest = (int)((nrest + 255) / 256);
   const unsigned grid = (unsigned)std::max(1, nb_hot + nb_cold + nb_rest);
   k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, (const double*)h->hot_rows,
-                                          (const double*)h->cold_rows, h->cold_off, h->cold_list, p,
+                                          (const S*)h->cold_rows, h->win_rows, h->cold_local_base, h->cold_off,
+                                          h->cold_list, p,
                                           (const S*)h->vec.D, lambda, w, h->n_split_pts, h->split_pts,
                                           h->split_rows, h->n_orphan_pts, h->partials, h->scal, pcg_mode ? 1 : 0,
                                           nb_hot, nb_cold);
