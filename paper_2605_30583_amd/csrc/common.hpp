@@ -279,6 +279,7 @@ void run_bj_apply(caspar_ba* h, const void* r, void* z);
 int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double tol, int max_iters,
             int check_every, void* x, double* rel_resid);
 double run_dot(caspar_ba* h, const void* a, const void* b, const void* wdiag);  // sum a b (w)
+void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx);  // g^T x, x^T r, x^T D x
 double run_absmax(caspar_ba* h, const void* a);
 void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
 void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);

@@ -205,86 +205,77 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     auto nobs = [&](int ti, const Tile& T) { return ti < t1 ? tile_nobs(T.info) : 0; };
     auto olane = [&](int k) { return min(lane, max(k, 1) - 1); };
     auto tile_at = [&](int ti) { return tiles[min(ti, t1 - 1)]; };
+    // Registers of one tile.  The loop is unrolled by two over a pair of
+    // these, so the set being computed and the set being filled swap roles
+    // instead of being copied.
+    struct Regs {
+      S col[12][2];             // Jacobian columns (stored blocks)
+      S pjv[3], dpv[3];         // p and D of the observation's point
+      S pcv[CamPad<S>::n];      // camera row of p
+      Cam<S> cpar;              // camera parameters (recomputed blocks)
+      double xj[3];             // the point (recomputed blocks)
+    };
+    // the requests made one tile ahead (tile descriptor T, nt observations,
+    // meta word mm of this lane)
+    auto request = [&](Regs& R, const Tile& T, int nt, uint32_t mm) {
+      if (PREFETCH_J && !RJ) JStore<S>::load(J, T.obs_begin + olane(nt), R.col);
+      if (PF_PT) {
+        const size_t b = 3 * (size_t)(T.pt_begin + (int)(mm >> kCamBits));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          R.pjv[k] = pp_base[b + k];
+          R.dpv[k] = dp_base[b + k];
+        }
+      }
+      if (PF_CAM) {
+        const int c = (int)(mm & ((1u << kCamBits) - 1));
+        load_cam_row<S>(p_cam, c, R.pcv);
+        if (RJ) {
+          R.cpar = load_cam_s<S>(cam_s, c);
+          const double* Xp = Xpts + 3 * (size_t)(T.pt_begin + (int)(mm >> kCamBits));
+#pragma unroll
+          for (int k = 0; k < 3; ++k) R.xj[k] = Xp[k];
+        }
+      }
+    };
     Tile tl = tiles[t], tln = tile_at(t + WAVES), tlnn = tile_at(t + 2 * WAVES);
     int n = tile_nobs(tl.info);
     uint32_t m = meta[tl.obs_begin + olane(n)];
     uint32_t mn = meta[tln.obs_begin + olane(nobs(t + WAVES, tln))];
-    S col[12][2];
-    if (!RJ) JStore<S>::load(J, tl.obs_begin + olane(n), col);
-    S pjv[3], dpv[3];
-    if (PF_PT) {
-      const size_t b = 3 * (size_t)(tl.pt_begin + (int)(m >> kCamBits));
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        pjv[k] = pp_base[b + k];
-        dpv[k] = dp_base[b + k];
-      }
-    }
-    S pcv[CamPad<S>::n];
-    Cam<S> cpar;
-    S xj[3];
-    if (PF_CAM) {
-      load_cam_row<S>(p_cam, (int)(m & ((1u << kCamBits) - 1)), pcv);
-      if (RJ) {
-        cpar = load_cam_s<S>(cam_s, (int)(m & ((1u << kCamBits) - 1)));
-        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + (int)(m >> kCamBits));
-#pragma unroll
-        for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
-      }
-    }
-    for (;;) {
+    Regs A, B;
+    request(A, tl, n, m);
+    if (!RJ && !PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), A.col);
+
+    // One tile: compute tile t from cur while the next tile's data comes
+    // into nxt.  Returns true after the wave's last tile.
+    auto step = [&](Regs& cur, Regs& nxt) -> bool {
       const bool act = lane < n;
       const int ci_raw = (int)(m & ((1u << kCamBits) - 1));
       const int lp_raw = (int)(m >> kCamBits);
       const int ci = act ? ci_raw : -1;
       const int lp = act ? lp_raw : 100 + lane;
-      // 1. gathers of the current tile: the camera row of p (with a
-      //    recomputed Jacobian also the camera parameters and the point;
-      //    without point prefetch also p and D of the point)
-      if (!PF_CAM) load_cam_row<S>(p_cam, ci_raw, pcv);
+      // 1. gathers of the current tile that the configuration does not
+      //    prefetch
+      if (!PF_CAM) load_cam_row<S>(p_cam, ci_raw, cur.pcv);
       if (!PF_PT) {
         const size_t b = 3 * (size_t)(tl.pt_begin + lp_raw);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          pjv[k] = pp_base[b + k];
-          dpv[k] = dp_base[b + k];
+          cur.pjv[k] = pp_base[b + k];
+          cur.dpv[k] = dp_base[b + k];
         }
       }
       if (RJ && !PF_CAM) {
-        cpar = load_cam_s<S>(cam_s, ci_raw);
+        cur.cpar = load_cam_s<S>(cam_s, ci_raw);
         const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + lp_raw);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) xj[k] = (S)Xp[k];
+        for (int k = 0; k < 3; ++k) cur.xj[k] = Xp[k];
       }
       // 2. requests for the next tiles, issued after the gathers so that
       //    waiting for the gathers does not wait for them
       __builtin_amdgcn_sched_barrier(0);
       const int tn = t + WAVES;
-      const int on = tln.obs_begin + olane(nobs(tn, tln));
-      S coln[12][2];
-      if (PREFETCH_J && !RJ) JStore<S>::load(J, on, coln);
-      S pjn[3], dpn[3];
-      if (PF_PT) {
-        const size_t b = 3 * (size_t)(tln.pt_begin + (int)(mn >> kCamBits));
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          pjn[k] = pp_base[b + k];
-          dpn[k] = dp_base[b + k];
-        }
-      }
-      S pcvn[CamPad<S>::n];
-      Cam<S> cparn;
-      double xjn[3];
-      if (PF_CAM) {
-        const int cin = (int)(mn & ((1u << kCamBits) - 1));
-        load_cam_row<S>(p_cam, cin, pcvn);
-        if (RJ) {
-          cparn = load_cam_s<S>(cam_s, cin);
-          const double* Xp = Xpts + 3 * (size_t)(tln.pt_begin + (int)(mn >> kCamBits));
-#pragma unroll
-          for (int k = 0; k < 3; ++k) xjn[k] = Xp[k];
-        }
-      }
+      request(nxt, tln, nobs(tn, tln), mn);
       const uint32_t mnn = meta[tlnn.obs_begin + olane(nobs(tn + WAVES, tlnn))];
       const Tile tl3 = tile_at(tn + 2 * WAVES);
       __builtin_amdgcn_sched_barrier(0);
@@ -295,20 +286,22 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 #pragma unroll
       for (int k = 0; k < 3; ++k) yp[k] = (S)0;
       if (act) {
+        S rcol[12][2];
+        S(&col)[12][2] = RJ ? rcol : cur.col;
         if (RJ) {
           S r0, r1;
-          snavely_jacobian<S>(cpar, xj[0], xj[1], xj[2], (S)0, (S)0, r0, r1, col);
+          snavely_jacobian<S>(cur.cpar, (S)cur.xj[0], (S)cur.xj[1], (S)cur.xj[2], (S)0, (S)0, r0, r1, rcol);
         }
         S q0 = (S)0, q1 = (S)0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-          q0 = fma(col[k][0], pcv[k], q0);
-          q1 = fma(col[k][1], pcv[k], q1);
+          q0 = fma(col[k][0], cur.pcv[k], q0);
+          q1 = fma(col[k][1], cur.pcv[k], q1);
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          q0 = fma(col[9 + k][0], pjv[k], q0);
-          q1 = fma(col[9 + k][1], pjv[k], q1);
+          q0 = fma(col[9 + k][0], cur.pjv[k], q0);
+          q1 = fma(col[9 + k][1], cur.pjv[k], q1);
         }
         pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
 #pragma unroll
@@ -351,13 +344,14 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       // lambda p^T D p, once per point
       if (head && (!split || tile_first(tl.info))) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pap = fma(lambda * (double)dpv[k] * (double)pjv[k], (double)pjv[k], pap);
+        for (int k = 0; k < 3; ++k)
+          pap = fma(lambda * (double)cur.dpv[k] * (double)cur.pjv[k], (double)cur.pjv[k], pap);
       }
       // the point rows of w (ordinary tiles)
       {
         S wv[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) wv[k] = fma((S)lambda * dpv[k], pjv[k], yp[k]);
+        for (int k = 0; k < 3; ++k) wv[k] = fma((S)lambda * cur.dpv[k], cur.pjv[k], yp[k]);
         const unsigned off = (unsigned)(3 * (tl.pt_begin + lp)) * (unsigned)sizeof(S);
         store3(w_rs, head && !split ? off : kDropOffset, wv);
       }
@@ -369,40 +363,19 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       }
       // 4. advance
       t = tn;
-      if (t >= t1) break;
+      if (t >= t1) return true;
       tl = tln;
       n = nobs(t, tl);
       m = mn;
       tln = tlnn;
       mn = mnn;
       tlnn = tl3;
-      if (PF_PT) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          pjv[k] = pjn[k];
-          dpv[k] = dpn[k];
-        }
-      }
-      if (PF_CAM) {
-#pragma unroll
-        for (int k = 0; k < CamPad<S>::n; ++k) pcv[k] = pcvn[k];
-        if (RJ) {
-          cpar = cparn;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) xj[k] = (S)xjn[k];
-        }
-      }
-      if (RJ) {
-        // the next tile's blocks are evaluated from its gathers
-      } else if (PREFETCH_J) {
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-          col[j][0] = coln[j][0];
-          col[j][1] = coln[j][1];
-        }
-      } else {
-        JStore<S>::load(J, tl.obs_begin + olane(n), col);
-      }
+      if (!RJ && !PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), nxt.col);
+      return false;
+    };
+    for (;;) {
+      if (step(A, B)) break;
+      if (step(B, A)) break;
     }
   }
   // lambda p^T D p of the camera blocks and of points without observations

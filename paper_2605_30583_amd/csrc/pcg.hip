@@ -352,6 +352,43 @@ __global__ __launch_bounds__(256) void k_dot(int64_t N, const S* __restrict__ a,
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = s;
 }
 
+// Partials of the three sums of the LM predicted decrease: g^T x, x^T r and
+// x^T D x, in one pass.
+template <typename S>
+__global__ __launch_bounds__(256) void k_pred_dots(int64_t N, const S* __restrict__ g, const S* __restrict__ x,
+                                                   const S* __restrict__ r, const S* __restrict__ D,
+                                                   double* __restrict__ partials) {
+  __shared__ double red[4];
+  double gx = 0.0, xr = 0.0, xdx = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double xv = x[i];
+    gx = fma((double)g[i], xv, gx);
+    xr = fma(xv, (double)r[i], xr);
+    xdx = fma(xv * xv, (double)D[i], xdx);
+  }
+  gx = block_sum(gx, red);
+  xr = block_sum(xr, red);
+  xdx = block_sum(xdx, red);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * kPartialWidth] = gx;
+    partials[(size_t)blockIdx.x * kPartialWidth + 1] = xr;
+    partials[(size_t)blockIdx.x * kPartialWidth + 2] = xdx;
+  }
+}
+
+__global__ void k_reduce_pred(int n, const double* __restrict__ partials, DevScalars* sc) {
+  __shared__ double red[16];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += partials[(size_t)i * kPartialWidth + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = block_sum(v[k], red);
+    if (threadIdx.x == 0) sc->red[4 + k] = t;
+  }
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_absmax(int64_t N, const S* __restrict__ a, double* __restrict__ partials) {
   __shared__ double red[4];
@@ -496,6 +533,26 @@ int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double to
   if (h->prec == CASPAR_FP64)
     return pcg_t<double>(h, lambda, (const double*)b, negate_b, tol, max_iters, check_every, rel_resid);
   return pcg_t<float>(h, lambda, (const float*)b, negate_b, tol, max_iters, check_every, rel_resid);
+}
+
+void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx) {
+  const int64_t N = h->N;
+  *gx = *xr = *xDx = 0.0;
+  if (N == 0) return;
+  const unsigned g = vec_grid(N);
+  if (h->prec == CASPAR_FP64)
+    k_pred_dots<double><<<g, 256, 0, h->stream>>>(N, (const double*)h->vec.g, (const double*)h->vec.x,
+                                                  (const double*)h->vec.r, (const double*)h->vec.D, h->partials);
+  else
+    k_pred_dots<float><<<g, 256, 0, h->stream>>>(N, (const float*)h->vec.g, (const float*)h->vec.x,
+                                                 (const float*)h->vec.r, (const float*)h->vec.D, h->partials);
+  CBA_LAUNCHED();
+  k_reduce_pred<<<1, 1024, 0, h->stream>>>((int)g, h->partials, h->scal);
+  CBA_LAUNCHED();
+  const DevScalars sc = read_scalars(h);
+  *gx = sc.red[4];
+  *xr = sc.red[5];
+  *xDx = sc.red[6];
 }
 
 double run_dot(caspar_ba* h, const void* a, const void* b, const void* e) {

@@ -200,9 +200,8 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
     const int k = run_pcg(h, lam, h->vec.g, true, o.pcg_tol, o.max_pcg_iters, o.pcg_check_every, nullptr, &rel);
     pcg_total += k;
     // pred = 1/2 (-g^T x + x^T r + lambda x^T D x)
-    const double gx = run_dot(h, h->vec.g, h->vec.x, nullptr);
-    const double xr = run_dot(h, h->vec.x, h->vec.r, nullptr);
-    const double xDx = run_dot(h, h->vec.x, h->vec.x, h->vec.D);
+    double gx, xr, xDx;
+    run_pred_dots(h, &gx, &xr, &xDx);
     const double pred = 0.5 * (-gx + xr + lam * xDx);
     run_retract(h, h->vec.x);
     const double Ft = run_cost(h, h->cam_trial, h->X_trial, false);
