@@ -169,7 +169,8 @@ struct caspar_ba {
   // parameters (float64, internal order)
   double* cam = nullptr;        // [nc][16]
   double* cam_trial = nullptr;
-  void* cam_s = nullptr;        // [nc][16] camera rows in the working precision (recomputed Jacobian)
+  void* cam_s = nullptr;        // [nc][16] camera rows in the working precision (linearisation, products)
+  void* cam_trial_s = nullptr;  // [nc][16] trial camera rows in float32 (trial cost of the mixed form)
   double* X = nullptr;          // [np][3]
   double* X_trial = nullptr;
 
@@ -239,7 +240,7 @@ struct Plan {
   struct Region {
     size_t off = 0, bytes = 0;
   };
-  Region cam, cam_trial, cam_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+  Region cam, cam_trial, cam_s, cam_trial_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;

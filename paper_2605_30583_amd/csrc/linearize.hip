@@ -35,7 +35,7 @@ template <typename S, bool STORE_J>
 __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __restrict__ tiles,
                                                     const uint32_t* __restrict__ meta,
                                                     const double* __restrict__ px,
-                                                    const double* __restrict__ cam,
+                                                    const S* __restrict__ camtab,
                                                     const double* __restrict__ X, void* J,
                                                     S* __restrict__ g, S* __restrict__ D,
                                                     double* __restrict__ Hpp,
@@ -43,25 +43,20 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
                                                     double* __restrict__ partials) {
   __shared__ double red[4];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  // wave-uniform tile index: descriptors come through the scalar cache
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int stride = gridDim.x * 4;
   double cost = 0.0;
-  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += gridDim.x * 4) {
-    const Tile tl = tiles[t];
-    const int n = tile_nobs(tl.info);
+  // One tile from its loaded inputs: residual, blocks (stored if STORE_J),
+  // cost, and per point the segmented sums of g_p and the upper triangle of
+  // H_p, written by the point's first lane.
+  auto tile = [&](const Tile& tl, int n, uint32_t m, const Cam<S>& c, const double* Xp, double2 q, int o) {
     const bool act = lane < n;
-    int lp = 100 + lane;
+    const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
     double v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
     if (act) {
-      const int o = tl.obs_begin + lane;
-      const uint32_t m = meta[o];
-      const int ci = (int)(m & ((1u << kCamBits) - 1));
-      lp = (int)(m >> kCamBits);
-      const int pi = tl.pt_begin + lp;
-      const Cam<S> c = load_cam<S>(cam, ci);
-      const double* Xp = X + 3 * (size_t)pi;
-      const double2 q = reinterpret_cast<const double2*>(px)[o];
       S r0, r1, col[12][2];
       snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
       if (STORE_J) JStore<S>::store(J, o, col);
@@ -87,8 +82,8 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
       const bool take = (lane + d < kWave) && olp == lp;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const double o = __shfl_down(v[k], d, kWave);
-        if (take) v[k] += o;
+        const double ov = __shfl_down(v[k], d, kWave);
+        if (take) v[k] += ov;
       }
     }
     const int prev = __shfl_up(lp, 1, kWave);
@@ -112,6 +107,31 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
         D[b + 2] = (S)clamp_diag(v[8]);
       }
     }
+  };
+  // Two tiles per iteration, both tiles' loads issued before either is
+  // computed.  Lanes past a tile's end, and a second tile past the range,
+  // read clamped in-range addresses; their values are unused.
+  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += 2 * stride) {
+    const int t2 = t + stride;
+    const Tile ta = tiles[t], tb = tiles[min(t2, n_tiles - 1)];
+    const int na = tile_nobs(ta.info), nb = t2 < n_tiles ? tile_nobs(tb.info) : 0;
+    const int oa = ta.obs_begin + min(lane, na - 1);
+    const int ob = tb.obs_begin + min(lane, max(nb, 1) - 1);
+    const uint32_t ma = meta[oa], mb = meta[ob];
+    // every load of both tiles first (camera rows in the working precision:
+    // these per-lane gathers bound the kernel, so float32 rows halve them);
+    // the barrier keeps the first tile's conversions from waiting on its
+    // loads before the second tile's are issued
+    const Cam<S> ca = load_cam_s<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)));
+    const Cam<S> cb = load_cam_s<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)));
+    const double* Xa = X + 3 * (size_t)(ta.pt_begin + (int)(ma >> kCamBits));
+    const double* Xb = X + 3 * (size_t)(tb.pt_begin + (int)(mb >> kCamBits));
+    const double xa[3] = {Xa[0], Xa[1], Xa[2]}, xb[3] = {Xb[0], Xb[1], Xb[2]};
+    const double2 qa = reinterpret_cast<const double2*>(px)[oa];
+    const double2 qb = reinterpret_cast<const double2*>(px)[ob];
+    __builtin_amdgcn_sched_barrier(0);
+    tile(ta, na, ma, ca, xa, qa, oa);
+    if (t2 < n_tiles) tile(tb, nb, mb, cb, xb, qb, ob);
   }
   const double tot = block_sum(cost, red);
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
@@ -239,27 +259,42 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restrict__ tiles,
                                               const uint32_t* __restrict__ meta,
                                               const double* __restrict__ px,
-                                              const double* __restrict__ cam,
+                                              const S* __restrict__ camtab,
                                               const double* __restrict__ X,
                                               double* __restrict__ partials) {
   __shared__ double red[4];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  // wave-uniform tile index: descriptors come through the scalar cache
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int stride = gridDim.x * 4;
   double cost = 0.0;
-  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += gridDim.x * 4) {
-    const Tile tl = tiles[t];
-    if (lane < tile_nobs(tl.info)) {
-      const int o = tl.obs_begin + lane;
-      const uint32_t m = meta[o];
-      const int ci = (int)(m & ((1u << kCamBits) - 1));
-      const int pi = tl.pt_begin + (int)(m >> kCamBits);
-      const Cam<S> c = load_cam<S>(cam, ci);
-      const double* Xp = X + 3 * (size_t)pi;
-      const double2 q = reinterpret_cast<const double2*>(px)[o];
-      S r0, r1;
-      snavely_residual<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1);
-      cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
-    }
+  // Two tiles per iteration, both tiles' loads issued before either is
+  // computed.  Lanes past a tile's end, and a second tile past the range,
+  // read clamped in-range addresses; their values are unused.
+  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += 2 * stride) {
+    const int t2 = t + stride;
+    const Tile ta = tiles[t], tb = tiles[min(t2, n_tiles - 1)];
+    const int na = tile_nobs(ta.info), nb = t2 < n_tiles ? tile_nobs(tb.info) : 0;
+    const int oa = ta.obs_begin + min(lane, na - 1);
+    const int ob = tb.obs_begin + min(lane, max(nb, 1) - 1);
+    const uint32_t ma = meta[oa], mb = meta[ob];
+    // every load of both tiles first (camera rows in the working precision:
+    // these per-lane gathers bound the kernel, so float32 rows halve them);
+    // the barrier keeps the first tile's conversions from waiting on its
+    // loads before the second tile's are issued
+    const Cam<S> ca = load_cam_s<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)));
+    const Cam<S> cb = load_cam_s<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)));
+    const double* Xa = X + 3 * (size_t)(ta.pt_begin + (int)(ma >> kCamBits));
+    const double* Xb = X + 3 * (size_t)(tb.pt_begin + (int)(mb >> kCamBits));
+    const double xa[3] = {Xa[0], Xa[1], Xa[2]}, xb[3] = {Xb[0], Xb[1], Xb[2]};
+    const double2 qa = reinterpret_cast<const double2*>(px)[oa];
+    const double2 qb = reinterpret_cast<const double2*>(px)[ob];
+    __builtin_amdgcn_sched_barrier(0);
+    S r0, r1;
+    snavely_residual<S>(ca, (S)xa[0], (S)xa[1], (S)xa[2], (S)qa.x, (S)qa.y, r0, r1);
+    if (lane < na) cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
+    snavely_residual<S>(cb, (S)xb[0], (S)xb[1], (S)xb[2], (S)qb.x, (S)qb.y, r0, r1);
+    if (lane < nb) cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
   }
   const double tot = block_sum(cost, red);
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
@@ -337,8 +372,18 @@ static inline unsigned nblk(int64_t n, int threads) {
   return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
 }
 
+// Workgroups of a 4-wave tile-walking kernel: as many as are resident on the
+// chip at once (a second, partly filled round would leave CUs idle), within
+// the partial-sum slots and the tiles.
+template <auto Kern>
 static unsigned tile_grid(int n_tiles) {
-  return (unsigned)std::max(1, std::min((n_tiles + 3) / 4, 2048));
+  static const int per_cu = [] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(Kern), 256, 0) != hipSuccess)
+      b = 1;
+    return std::max(b, 1);
+  }();
+  return (unsigned)std::max(1, std::min({(n_tiles + 3) / 4, per_cu * kNumCUs, kMaxPartials}));
 }
 
 template <typename S>
@@ -346,18 +391,23 @@ static void linearize_t(caspar_ba* h) {
   hipStream_t st = h->stream;
   S* g = (S*)h->vec.g;
   S* D = (S*)h->vec.D;
-  const unsigned tg = tile_grid(h->n_tiles);
-  if (h->rj && h->nc > 0) {
+  const unsigned tg = h->rj ? tile_grid<k_lin_points<S, false>>(h->n_tiles) : tile_grid<k_lin_points<S, true>>(h->n_tiles);
+  // camera rows in the working precision (float32 rows feed the point side
+  // and the products; float64 reads the master rows unless the products
+  // recompute their blocks)
+  const bool cast = sizeof(S) == 4 || h->rj;
+  if (cast && h->nc > 0) {
     k_cam_cast<S><<<nblk((int64_t)h->nc * kCamStride, 256), 256, 0, st>>>(h->nc * kCamStride, h->cam,
                                                                           (S*)h->cam_s);
     CBA_LAUNCHED();
   }
+  const S* camtab = cast ? (const S*)h->cam_s : (const S*)h->cam;
   if (h->n_tiles > 0) {
     if (h->rj)
-      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, g, D,
+      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, h->X, h->J, g, D,
                                                  h->Hpp, h->split_rows, h->nc, h->partials);
     else
-      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, g, D,
+      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, h->X, h->J, g, D,
                                                 h->Hpp, h->split_rows, h->nc, h->partials);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
@@ -399,11 +449,19 @@ void run_linearize(caspar_ba* h) {
 double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
   if (h->n_tiles == 0) return 0.0;
   hipStream_t st = h->stream;
-  const unsigned tg = tile_grid(h->n_tiles);
-  if (fp64 || h->prec == CASPAR_FP64)
+  const bool f64 = fp64 || h->prec == CASPAR_FP64;
+  const unsigned tg = f64 ? tile_grid<k_cost<double>>(h->n_tiles) : tile_grid<k_cost<float>>(h->n_tiles);
+  if (f64) {
     k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials);
-  else
-    k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials);
+  } else {
+    // float32 rows of the cameras being evaluated, so the residual kernel
+    // gathers 64 bytes per observation instead of 128
+    k_cam_cast<float><<<nblk((int64_t)h->nc * kCamStride, 256), 256, 0, st>>>(h->nc * kCamStride, cam,
+                                                                              (float*)h->cam_trial_s);
+    CBA_LAUNCHED();
+    k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, (const float*)h->cam_trial_s, X,
+                                      h->partials);
+  }
   CBA_LAUNCHED();
   k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 1);
   CBA_LAUNCHED();
