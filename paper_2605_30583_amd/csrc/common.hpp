@@ -171,6 +171,7 @@ struct caspar_ba {
   double* cam_trial = nullptr;
   void* cam_s = nullptr;        // [nc][16] camera rows in the working precision (linearisation, products)
   void* cam_trial_s = nullptr;  // [nc][16] trial camera rows in float32 (trial cost of the mixed form)
+  void* pts_s = nullptr;        // points in the working precision: float32 [np][4], or X itself in float64
   double* X = nullptr;          // [np][3]
   double* X_trial = nullptr;
 
@@ -240,7 +241,7 @@ struct Plan {
   struct Region {
     size_t off = 0, bytes = 0;
   };
-  Region cam, cam_trial, cam_s, cam_trial_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+  Region cam, cam_trial, cam_s, cam_trial_s, pts_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
@@ -250,6 +251,12 @@ struct Plan {
 bool make_plan(int nc, int np, int64_t no, int mode, Plan& plan);
 
 inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
+
+// Points in the working precision: the float32 copy written at each
+// linearisation, or the (current) float64 master rows.
+inline const void* pts_table(const caspar_ba* h) {
+  return h->prec == CASPAR_FP64 ? static_cast<const void*>(h->X) : h->pts_s;
+}
 
 // The fused product accumulates camera sums in float64 in both precisions
 // (ds_add_f64 in LDS measured faster than ds_add_f32 on this chip).

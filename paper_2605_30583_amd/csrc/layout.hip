@@ -94,6 +94,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.cam_trial, (size_t)nc * kCamStride * 8);
   take(p.cam_s, (size_t)nc * kCamStride * s);
   take(p.cam_trial_s, (size_t)nc * kCamStride * 4);
+  take(p.pts_s, prec == CASPAR_FP64 ? 16 : (size_t)np * 16);
   take(p.X, (size_t)np * 3 * 8);
   take(p.X_trial, (size_t)np * 3 * 8);
   take(p.cam_c2i, (size_t)nc * 4);
@@ -683,6 +684,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->cam_trial = (double*)(ws + plan.cam_trial.off);
     h->cam_s = ws + plan.cam_s.off;
     h->cam_trial_s = ws + plan.cam_trial_s.off;
+    h->pts_s = ws + plan.pts_s.off;
     h->X = (double*)(ws + plan.X.off);
     h->X_trial = (double*)(ws + plan.X_trial.off);
     h->cam_c2i = (int*)(ws + plan.cam_c2i.off);

@@ -28,6 +28,12 @@ __global__ void k_cam_cast(int n, const double* __restrict__ cam, S* __restrict_
   if (i < n) out[i] = (S)cam[i];
 }
 
+// float32 point rows (x, y, z, 0), one 16-byte load each.
+__global__ void k_point_cast(int np, const double* __restrict__ X, float4* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) out[i] = make_float4((float)X[3 * (size_t)i], (float)X[3 * (size_t)i + 1], (float)X[3 * (size_t)i + 2], 0.f);
+}
+
 // ---------------------------------------------------------------------------
 // Point-major linearisation.
 // ---------------------------------------------------------------------------
@@ -36,7 +42,7 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
                                                     const uint32_t* __restrict__ meta,
                                                     const double* __restrict__ px,
                                                     const S* __restrict__ camtab,
-                                                    const double* __restrict__ X, void* J,
+                                                    const S* __restrict__ pts, void* J,
                                                     S* __restrict__ g, S* __restrict__ D,
                                                     double* __restrict__ Hpp,
                                                     double* __restrict__ split_rows, int nc,
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
   // One tile from its loaded inputs: residual, blocks (stored if STORE_J),
   // cost, and per point the segmented sums of g_p and the upper triangle of
   // H_p, written by the point's first lane.
-  auto tile = [&](const Tile& tl, int n, uint32_t m, const Cam<S>& c, const double* Xp, double2 q, int o) {
+  auto tile = [&](const Tile& tl, int n, uint32_t m, const Cam<S>& c, const S (&Xp)[3], double2 q, int o) {
     const bool act = lane < n;
     const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
     double v[9];
@@ -58,7 +64,7 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
     if (act) {
       S r0, r1, col[12][2];
-      snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+      snavely_jacobian<S>(c, Xp[0], Xp[1], Xp[2], (S)q.x, (S)q.y, r0, r1, col);
       if (STORE_J) JStore<S>::store(J, o, col);
       cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
       double jp[3][2];
@@ -124,9 +130,9 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
     // loads before the second tile's are issued
     const Cam<S> ca = load_cam_s<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)));
     const Cam<S> cb = load_cam_s<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)));
-    const double* Xa = X + 3 * (size_t)(ta.pt_begin + (int)(ma >> kCamBits));
-    const double* Xb = X + 3 * (size_t)(tb.pt_begin + (int)(mb >> kCamBits));
-    const double xa[3] = {Xa[0], Xa[1], Xa[2]}, xb[3] = {Xb[0], Xb[1], Xb[2]};
+    S xa[3], xb[3];
+    load_point<S>(pts, (size_t)(ta.pt_begin + (int)(ma >> kCamBits)), xa);
+    load_point<S>(pts, (size_t)(tb.pt_begin + (int)(mb >> kCamBits)), xb);
     const double2 qa = reinterpret_cast<const double2*>(px)[oa];
     const double2 qb = reinterpret_cast<const double2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
                                                   const int* __restrict__ cm_pt,
                                                   const double* __restrict__ cm_px,
                                                   const double* __restrict__ cam,
-                                                  const double* __restrict__ X,
+                                                  const S* __restrict__ pts,
                                                   double* __restrict__ rows) {
   __shared__ double lds[4][kCamRowWidth];
   const Chunk ch = chunks[blockIdx.x];
@@ -185,11 +191,11 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
 #pragma unroll
   for (int k = 0; k < kCamRowWidth; ++k) acc[k] = 0.0;
   for (int j = ch.begin + threadIdx.x; j < ch.end; j += blockDim.x) {
-    const int pi = cm_pt[j];
-    const double* Xp = X + 3 * (size_t)pi;
+    S xp[3];
+    load_point<S>(pts, (size_t)cm_pt[j], xp);
     const double2 q = reinterpret_cast<const double2*>(cm_px)[j];
     S r0, r1, col[12][2];
-    snavely_jacobian<S>(c, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+    snavely_jacobian<S>(c, xp[0], xp[1], xp[2], (S)q.x, (S)q.y, r0, r1, col);
     double jc[9][2];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -402,12 +408,17 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   const S* camtab = cast ? (const S*)h->cam_s : (const S*)h->cam;
+  if (sizeof(S) == 4 && h->np > 0) {
+    k_point_cast<<<nblk(h->np, 256), 256, 0, st>>>(h->np, h->X, (float4*)h->pts_s);
+    CBA_LAUNCHED();
+  }
+  const S* ptab = (const S*)pts_table(h);
   if (h->n_tiles > 0) {
     if (h->rj)
-      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, h->X, h->J, g, D,
+      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
                                                  h->Hpp, h->split_rows, h->nc, h->partials);
     else
-      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, h->X, h->J, g, D,
+      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
                                                 h->Hpp, h->split_rows, h->nc, h->partials);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
@@ -425,7 +436,7 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->n_chunks > 0) {
-    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, h->X, h->chunk_rows);
+    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, ptab, h->chunk_rows);
     CBA_LAUNCHED();
   }
   if (h->nc > 0) {

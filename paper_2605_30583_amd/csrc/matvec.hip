@@ -147,7 +147,7 @@ __device__ inline void store3(__amdgpu_buffer_rsrc_t rs, unsigned off, const dou
 template <typename S, bool RJ>
 __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-    const void* __restrict__ J, const S* __restrict__ cam_s, const double* __restrict__ Xpts,
+    const void* __restrict__ J, const S* __restrict__ cam_s, const S* __restrict__ pts_s,
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
@@ -213,7 +213,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       S pjv[3], dpv[3];         // p and D of the observation's point
       S pcv[CamPad<S>::n];      // camera row of p
       Cam<S> cpar;              // camera parameters (recomputed blocks)
-      double xj[3];             // the point (recomputed blocks)
+      S xj[3];                  // the point (recomputed blocks)
     };
     // the requests made one tile ahead (tile descriptor T, nt observations,
     // meta word mm of this lane)
@@ -232,9 +232,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
         load_cam_row<S>(p_cam, c, R.pcv);
         if (RJ) {
           R.cpar = load_cam_s<S>(cam_s, c);
-          const double* Xp = Xpts + 3 * (size_t)(T.pt_begin + (int)(mm >> kCamBits));
-#pragma unroll
-          for (int k = 0; k < 3; ++k) R.xj[k] = Xp[k];
+          load_point<S>(pts_s, (size_t)(T.pt_begin + (int)(mm >> kCamBits)), R.xj);
         }
       }
     };
@@ -267,9 +265,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       }
       if (RJ && !PF_CAM) {
         cur.cpar = load_cam_s<S>(cam_s, ci_raw);
-        const double* Xp = Xpts + 3 * (size_t)(tl.pt_begin + lp_raw);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) cur.xj[k] = Xp[k];
+        load_point<S>(pts_s, (size_t)(tl.pt_begin + lp_raw), cur.xj);
       }
       // 2. requests for the next tiles, issued after the gathers so that
       //    waiting for the gathers does not wait for them
@@ -290,7 +286,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
         S(&col)[12][2] = RJ ? rcol : cur.col;
         if (RJ) {
           S r0, r1;
-          snavely_jacobian<S>(cur.cpar, (S)cur.xj[0], (S)cur.xj[1], (S)cur.xj[2], (S)0, (S)0, r0, r1, rcol);
+          snavely_jacobian<S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], (S)0, (S)0, r0, r1, rcol);
         }
         S q0 = (S)0, q1 = (S)0;
 #pragma unroll
@@ -509,7 +505,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
   if (lds > 65536)
     CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   timing_mark_start(h);
-  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, h->X,
+  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, (const S*)pts_table(h),
                                      (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
                                      h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows, h->win_rows,
                                      h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,

@@ -15,6 +15,23 @@ struct Cam {
   T f, k1, k2;
 };
 
+// Point coordinates in the working precision: float32 rows (x, y, z, 0) read
+// with one 16-byte load, or the float64 master rows of 3.
+template <typename S>
+__device__ inline void load_point(const S* __restrict__ tab, size_t i, S (&x)[3]);
+template <>
+__device__ inline void load_point<float>(const float* __restrict__ tab, size_t i, float (&x)[3]) {
+  const float4 v = reinterpret_cast<const float4*>(tab)[i];
+  x[0] = v.x;
+  x[1] = v.y;
+  x[2] = v.z;
+}
+template <>
+__device__ inline void load_point<double>(const double* __restrict__ tab, size_t i, double (&x)[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = tab[3 * i + k];
+}
+
 // Loads one 16-double camera row [R(9) t(3) f k1 k2 pad] (128-byte aligned).
 template <typename T>
 __device__ inline Cam<T> load_cam(const double* __restrict__ camtab, int c) {
