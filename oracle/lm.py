@@ -18,6 +18,10 @@ Stops early when ||g||_inf <= grad_tol * max(1, ||g_0||_inf) or F <= min_cost.
 Defaults: lambda_0 = 1e-2, the inverse of the initial trust-region radius
 100 used in Section VI.
 
+With a robust loss (robust.py) the cost is 1/2 sum rho(|r|^2) and each
+linearisation uses the IRLS-scaled residuals and blocks; the gain ratio
+compares the robust cost decrease with that weighted model's prediction.
+
 Pins (tests/test_oracle_lm.py): zero-noise problems converge to F ~ 0,
 accepted costs decrease monotonically, the noisy optimum matches the
 chi-square expectation, an independent solver (scipy least_squares on an
@@ -30,7 +34,7 @@ import dataclasses
 
 import numpy as np
 
-from . import camera, linear, pcg as pcg_mod
+from . import camera, linear, pcg as pcg_mod, robust
 
 
 @dataclasses.dataclass
@@ -45,6 +49,8 @@ class LMOptions:
     grad_tol: float = 1e-12
     min_cost: float = 1e-30
     nu_max: float = 2.0 ** 60
+    loss: str = "trivial"           # "trivial" | "huber" | "cauchy" (robust.py)
+    loss_scale: float = 1.0
 
 
 @dataclasses.dataclass
@@ -68,10 +74,13 @@ class LMResult:
     stop_reason: str
 
 
-def _linearize(state, obs_cam, obs_pt, obs_px):
-    r, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
+def _linearize(state, obs_cam, obs_pt, obs_px, loss="trivial", scale=1.0):
+    if loss == "trivial":
+        r, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
+        F = 0.5 * float(np.sum(r * r))
+    else:
+        F, r, Jc, Jp, _ = robust.linearize(state, obs_cam, obs_pt, obs_px, loss, scale)
     J = linear.jacobian_csr(Jc, Jp, obs_cam, obs_pt, state.n_cams, state.n_points)
-    F = 0.5 * float(np.sum(r * r))
     g = linear.gradient(J, r)
     D = linear.damping_diagonal(J)
     return F, J, g, D
@@ -95,7 +104,8 @@ def solve_step(J, D, lam, b, n_cams, n_points, opts: LMOptions):
 def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None = None) -> LMResult:
     opts = opts or LMOptions()
     state = state.copy()
-    F, J, g, D = _linearize(state, obs_cam, obs_pt, obs_px)
+    lin = lambda st: _linearize(st, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
+    F, J, g, D = lin(state)
     F0 = F
     g0 = float(np.max(np.abs(g))) if g.size else 0.0
     lam, nu = opts.lambda0, 2.0
@@ -112,12 +122,12 @@ def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None =
         delta, r_in, k = solve_step(J, D, lam, b, state.n_cams, state.n_points, opts)
         pred = 0.5 * float(b @ delta + delta @ r_in + lam * delta @ (D * delta))
         trial = state.retract(delta)
-        Ft = camera.cost(trial, obs_cam, obs_pt, obs_px)
+        Ft = robust.cost(trial, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
         rho = (F - Ft) / pred if (pred > 0.0 and np.isfinite(Ft)) else -np.inf
         lam_used = lam
         if rho > 0.0:
             state = trial
-            F, J, g, D = _linearize(state, obs_cam, obs_pt, obs_px)
+            F, J, g, D = lin(state)
             lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
             nu = 2.0
             accepted = True

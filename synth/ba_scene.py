@@ -15,7 +15,11 @@ available here, so scenes of the same structure are synthesised:
   angle-axis + N(0, 0.01^2), translation + N(0, 0.05^2), points
   + N(0, 0.05^2); f, k1, k2 exact.
 
-Draw order is fixed: k1/k2, points, visibility, noise, perturbations.
+* optionally a fraction of observations with gross outliers: their noise is
+  replaced by N(0, outlier_px^2) (drawn last).
+
+Draw order is fixed: k1/k2, points, visibility, noise, perturbations,
+outliers.
 
 Only random draws and the scene layout live here.  The observed pixels
 (prediction + noise) are formed by the consumer with its own projection,
@@ -155,7 +159,7 @@ def make_scene(n_cams: int, n_points: int, seed: int, *, k_values=(4,), k_probs=
                zipf_s: float | None = None, radius: float = 10.0, focal: float = 500.0,
                kdist_std: float = 1e-3, point_half_width: float = 2.0,
                noise_px: float = 1.0, rot_std: float = 0.01, trans_std: float = 0.05,
-               point_std: float = 0.05) -> Scene:
+               point_std: float = 0.05, outlier_frac: float = 0.0, outlier_px: float = 40.0) -> Scene:
     """Draw one synthetic scene (see module docstring for the recipe)."""
     rng = np.random.default_rng(seed)
     R, t = _look_at_frames(n_cams, radius)
@@ -177,11 +181,18 @@ def make_scene(n_cams: int, n_points: int, seed: int, *, k_values=(4,), k_probs=
     cams0[:, 0:3] += rng.normal(0.0, rot_std, size=(n_cams, 3))
     cams0[:, 3:6] += rng.normal(0.0, trans_std, size=(n_cams, 3))
     pts0 = pts + rng.normal(0.0, point_std, size=(n_points, 3))
+    if outlier_frac > 0.0:
+        # gross outliers, drawn after everything else so the rest of the scene
+        # is the same as without them: these observations get N(0, outlier_px)
+        # pixel errors instead of the ordinary noise
+        sel = rng.random(obs_cam.shape[0]) < outlier_frac
+        noise[sel] = rng.normal(0.0, outlier_px, size=(int(sel.sum()), 2))
     return Scene(cams, pts, obs_cam, obs_pt, noise, cams0, pts0)
 
 
 # The five workloads: tiny, medium, BAL-shaped 1.7k cameras, medium with the
-# adjoint (same scene as medium), and the large Zipf-skewed BAL shape.
+# adjoint (same scene as medium), and the large Zipf-skewed BAL shape; plus
+# the tiny scene with planted outliers for the robust losses.
 SCENE_CONFIGS = {
     "tiny":   dict(n_cams=16, n_points=1_000, seed=1, k_values=(4,), k_probs=(1.0,)),
     "medium": dict(n_cams=250, n_points=50_000, seed=2, k_values=(6,), k_probs=(1.0,)),
@@ -189,6 +200,9 @@ SCENE_CONFIGS = {
     "medium_adjoint": dict(n_cams=250, n_points=50_000, seed=2, k_values=(6,), k_probs=(1.0,)),
     "large_zipf": dict(n_cams=13_700, n_points=4_400_000, seed=5, k_values=(6, 7),
                        k_probs=(0.41, 0.59), zipf_s=1.1),
+    # robust losses: the tiny scene with 5% gross outliers (40 px)
+    "tiny_outliers": dict(n_cams=16, n_points=1_000, seed=1, k_values=(4,), k_probs=(1.0,),
+                          outlier_frac=0.05, outlier_px=40.0),
 }
 
 

@@ -1,5 +1,6 @@
 """Writes tests/golden/lm_reference.json: the oracle's Levenberg-Marquardt
-results on the tiny and medium synthetic workloads.
+results on the synthetic workloads (plain least squares, and the robust
+losses on the tiny scene with planted outliers).
 
 Calls only synth/ and oracle/ (exact Schur-complement steps, float64).
 Run from the repository root:
@@ -19,7 +20,14 @@ sys.path.insert(0, ROOT)
 from oracle import camera, lm  # noqa: E402
 from synth import scene_config  # noqa: E402
 
-RUNS = {"tiny": 20, "medium": 30, "bal1700": 20}
+# run name -> (scene, LM iterations, loss, loss scale in pixels)
+RUNS = {
+    "tiny": ("tiny", 20, "trivial", 1.0),
+    "medium": ("medium", 30, "trivial", 1.0),
+    "bal1700": ("bal1700", 20, "trivial", 1.0),
+    "tiny_outliers_huber": ("tiny_outliers", 20, "huber", 3.0),
+    "tiny_outliers_cauchy": ("tiny_outliers", 20, "cauchy", 3.0),
+}
 
 
 def main():
@@ -31,14 +39,18 @@ def main():
         out["runs"] = json.load(open(path))["runs"]
     names = sys.argv[1:] or list(RUNS)
     for name in names:
-        iters = RUNS[name]
-        sc = scene_config(name)
+        scene, iters, loss, scale = RUNS[name]
+        sc = scene_config(scene)
         st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
         px = camera.project(st_true, sc.obs_cam, sc.obs_pt) + sc.noise
         st = camera.State.from_bal(sc.cams_init, sc.points_init)
         t = time.time()
-        res = lm.solve(st, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=iters, inner="schur"))
+        res = lm.solve(st, sc.obs_cam, sc.obs_pt, px,
+                       lm.LMOptions(max_iters=iters, inner="schur", loss=loss, loss_scale=scale))
         out["runs"][name] = {
+            "scene": scene,
+            "loss": loss,
+            "loss_scale": scale,
             "max_iters": iters,
             "initial_cost": res.initial_cost,
             "final_cost": res.final_cost,
