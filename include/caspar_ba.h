@@ -67,6 +67,14 @@ enum { CASPAR_FP64 = 0, CASPAR_FP32_MIXED = 1 };
  * blocks are bitwise the same as the stored ones. */
 enum { CASPAR_RECOMPUTE_JACOBIAN = 0x10 };
 
+/* Robust losses of the squared residual norm s = |r_o|^2 (caspar_ba_set_loss).
+ * The paper's residual formulation leaves weighting schemes and robust losses
+ * to the user (Sec. VI-A); these three, with scale c > 0 in pixels:
+ *   CASPAR_LOSS_TRIVIAL  rho(s) = s
+ *   CASPAR_LOSS_HUBER    rho(s) = s for s <= c^2, 2 c sqrt(s) - c^2 otherwise
+ *   CASPAR_LOSS_CAUCHY   rho(s) = c^2 log(1 + s / c^2) */
+enum { CASPAR_LOSS_TRIVIAL = 0, CASPAR_LOSS_HUBER = 1, CASPAR_LOSS_CAUCHY = 2 };
+
 enum {
   CASPAR_OK = 0,
   CASPAR_EINVAL = -1,   /* bad argument, index out of range, non-finite input */
@@ -87,6 +95,10 @@ typedef struct caspar_solve_opts {
   double min_cost;       /* stop when the cost F <= min_cost; default 1e-30 */
   int32_t pcg_check_every; /* host polls PCG convergence every this many iterations; default 4 */
   int32_t flags;         /* reserved, 0 */
+  double pred_tol;       /* stop when the step's predicted decrease pred <= pred_tol * F; default 0
+                            (never).  Once pred falls below the resolution of F (about 1e-16 F) the
+                            gain ratio is rounding noise; a few DBL_EPSILON stops the solve there
+                            instead of accepting or rejecting steps by chance. */
 } caspar_solve_opts;
 
 /* Per-solve statistics (host). */
@@ -94,7 +106,7 @@ typedef struct caspar_solve_stats {
   int32_t lm_iters;        /* iterations run (accepted + rejected) */
   int32_t accepted;        /* accepted trials */
   int32_t pcg_iters_total; /* PCG iterations (matrix products) over all LM iterations */
-  int32_t stop_reason;     /* 0 max iterations, 1 gradient, 2 cost */
+  int32_t stop_reason;     /* 0 max iterations, 1 gradient, 2 cost, 3 predicted decrease */
   double initial_cost;     /* F = 1/2 sum |r|^2 at the start */
   double final_cost;       /* F at the returned parameters */
   double final_lambda;
@@ -151,6 +163,18 @@ CASPAR_API int caspar_ba_get_params(caspar_ba* h, double* cams, double* points);
  * restart. */
 CASPAR_API int caspar_ba_set_params(caspar_ba* h, const double* cams, const double* points);
 
+/* Select the robust loss (default CASPAR_LOSS_TRIVIAL).  The cost becomes
+ * F = 1/2 sum_o rho(|r_o|^2) and every linearisation is iteratively
+ * reweighted: with w_o = rho'(|r_o|^2) held fixed until the next
+ * linearisation, residuals and Jacobian blocks are scaled by sqrt(w_o), so the
+ * normal equations are (J^T W J + lambda D) delta = -J^T W r with
+ * D = clamp(diag J^T W J) and J^T W r the exact gradient of F.  The gain
+ * ratio compares the decrease of F with that weighted model's prediction.
+ * The parity hooks (linearize, matvec, pcg, cost_fp64) and the adjoint use
+ * the same weighted system; the adjoint holds the weights fixed.  scale must
+ * be finite and > 0 (CASPAR_EINVAL otherwise, or for an unknown kind). */
+CASPAR_API int caspar_ba_set_loss(caspar_ba* h, int32_t kind, double scale);
+
 /* Replace the observed pixels (dev [n_obs][2], caller order). */
 CASPAR_API int caspar_ba_set_observations(caspar_ba* h, const double* obs_px);
 
@@ -176,7 +200,9 @@ CASPAR_API int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const d
 /* ---- Parity hooks: single steps of the hot path at the current parameters ---- */
 
 /* Linearise (residuals, Jacobian blocks, cost, gradient g = J^T r, damping
- * diagonal D = clamp(diag J^T J, 1e-6, 1e32)).  cost (host) may be NULL;
+ * diagonal D = clamp(diag J^T J, 1e-6, 1e32)); with a robust loss the
+ * residuals and blocks are the sqrt(w)-scaled ones and the cost is
+ * 1/2 sum rho(|r|^2) (see caspar_ba_set_loss).  cost (host) may be NULL;
  * resid (dev [n_obs][2]), jac_cam (dev [n_obs][2][9]), jac_pt
  * (dev [n_obs][2][3]), grad (dev [N]) and diag (dev [N]) may each be NULL.
  * Outputs are float64 in caller order (FP32_MIXED values are widened). */

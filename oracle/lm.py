@@ -13,7 +13,9 @@ One iteration = one inner solve plus one trial, accepted or not:
                         nu = 2
   otherwise:            lambda *= nu, nu *= 2
   lambda clamped to [lambda_min, lambda_max].
-Stops early when ||g||_inf <= grad_tol * max(1, ||g_0||_inf) or F <= min_cost.
+Stops early when ||g||_inf <= grad_tol * max(1, ||g_0||_inf), F <= min_cost,
+or (if pred_tol > 0) the step's predicted decrease pred <= pred_tol * F: below
+the resolution of F the gain ratio is rounding noise.
 
 Defaults: lambda_0 = 1e-2, the inverse of the initial trust-region radius
 100 used in Section VI.
@@ -49,6 +51,7 @@ class LMOptions:
     grad_tol: float = 1e-12
     min_cost: float = 1e-30
     nu_max: float = 2.0 ** 60
+    pred_tol: float = 0.0           # stop when pred <= pred_tol * F (0: never)
     loss: str = "trivial"           # "trivial" | "huber" | "cauchy" (robust.py)
     loss_scale: float = 1.0
 
@@ -121,6 +124,9 @@ def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None =
         b = -g
         delta, r_in, k = solve_step(J, D, lam, b, state.n_cams, state.n_points, opts)
         pred = 0.5 * float(b @ delta + delta @ r_in + lam * delta @ (D * delta))
+        if opts.pred_tol > 0.0 and pred <= opts.pred_tol * F:
+            reason = "pred"
+            break
         trial = state.retract(delta)
         Ft = robust.cost(trial, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
         rho = (F - Ft) / pred if (pred > 0.0 and np.isfinite(Ft)) else -np.inf

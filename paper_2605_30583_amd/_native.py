@@ -10,6 +10,7 @@ FP64 = 0
 FP32_MIXED = 1
 ADJ_GAUGE_PROJECT = 1
 RECOMPUTE_JACOBIAN = 0x10
+LOSS_TRIVIAL, LOSS_HUBER, LOSS_CAUCHY = 0, 1, 2
 STATUS = {0: "CASPAR_OK", -1: "CASPAR_EINVAL", -2: "CASPAR_EHIP", -3: "CASPAR_ENOMEM", -4: "CASPAR_ENUMERIC"}
 
 
@@ -17,7 +18,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("lambda0", C.c_double), ("pcg_tol", C.c_double), ("max_lm_iters", C.c_int32),
                 ("max_pcg_iters", C.c_int32), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
                 ("grad_tol", C.c_double), ("min_cost", C.c_double), ("pcg_check_every", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("pred_tol", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -48,6 +49,7 @@ SIGNATURES = [
     ("caspar_ba_get_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_observations", C.c_int, [_P, _P]),
+    ("caspar_ba_set_loss", C.c_int, [_P, C.c_int32, C.c_double]),
     ("caspar_ba_backward", C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, _P,
                                      C.POINTER(C.c_int32)]),
     ("caspar_ba_linearize", C.c_int, [_P, _D, _P, _P, _P, _P, _P]),

@@ -44,6 +44,7 @@ class SolveOptions:
     grad_tol: float = 1e-12
     min_cost: float = 1e-30
     pcg_check_every: int = 4
+    pred_tol: float = 0.0
 
     def to_c(self) -> _native.SolveOpts:
         o = _native.SolveOpts()
@@ -139,6 +140,15 @@ class BundleAdjuster:
         if points is not None:
             _dev(points, torch.float64, (self.n_points, 3), "points")
         check(self._lib.caspar_ba_set_params(self._h, _ptr(cams), _ptr(points)))
+
+    LOSSES = {"trivial": _native.LOSS_TRIVIAL, "huber": _native.LOSS_HUBER, "cauchy": _native.LOSS_CAUCHY}
+
+    def set_loss(self, kind: str = "trivial", scale: float = 1.0):
+        """Robust loss of the squared residual norm (caspar_ba_set_loss):
+        "trivial", "huber" or "cauchy" with scale in pixels."""
+        if kind not in self.LOSSES:
+            raise ValueError(f"unknown loss {kind!r}; expected one of {sorted(self.LOSSES)}")
+        check(self._lib.caspar_ba_set_loss(self._h, self.LOSSES[kind], float(scale)))
 
     def set_observations(self, obs_px):
         _dev(obs_px, torch.float64, (self.n_obs, 2), "obs_px")

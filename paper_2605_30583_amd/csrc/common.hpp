@@ -145,6 +145,8 @@ struct caspar_ba {
   int nc = 0, np = 0;
   int no = 0;
   int prec = CASPAR_FP64;
+  int loss = CASPAR_LOSS_TRIVIAL;  // robust loss of the squared residual norm
+  double loss_c = 1.0;             // its scale (pixels)
   bool rj = false;        // Jacobian recomputed in every product instead of stored
   int N = 0;              // 9 nc + 3 np
   hipStream_t stream = nullptr;
@@ -172,6 +174,7 @@ struct caspar_ba {
   void* cam_s = nullptr;        // [nc][16] camera rows in the working precision (linearisation, products)
   void* cam_trial_s = nullptr;  // [nc][16] trial camera rows in float32 (trial cost of the mixed form)
   void* pts_s = nullptr;        // points in the working precision: float32 [np][4], or X itself in float64
+  void* wts = nullptr;          // [no] IRLS weights rho'(|r|^2) of the last linearisation (robust losses)
   double* X = nullptr;          // [np][3]
   double* X_trial = nullptr;
 
@@ -241,7 +244,7 @@ struct Plan {
   struct Region {
     size_t off = 0, bytes = 0;
   };
-  Region cam, cam_trial, cam_s, cam_trial_s, pts_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+  Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
@@ -251,6 +254,12 @@ struct Plan {
 bool make_plan(int nc, int np, int64_t no, int mode, Plan& plan);
 
 inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
+
+// IRLS weights for a kernel: null with the trivial loss.
+template <typename S>
+inline const S* weights_of(const caspar_ba* h) {
+  return h->loss == CASPAR_LOSS_TRIVIAL ? nullptr : static_cast<const S*>(h->wts);
+}
 
 // Points in the working precision: the float32 copy written at each
 // linearisation, or the (current) float64 master rows.

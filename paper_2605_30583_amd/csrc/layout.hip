@@ -95,6 +95,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.cam_s, (size_t)nc * kCamStride * s);
   take(p.cam_trial_s, (size_t)nc * kCamStride * 4);
   take(p.pts_s, prec == CASPAR_FP64 ? 16 : (size_t)np * 16);
+  take(p.wts, (size_t)no * s + 16);
   take(p.X, (size_t)np * 3 * 8);
   take(p.X_trial, (size_t)np * 3 * 8);
   take(p.cam_c2i, (size_t)nc * 4);
@@ -639,6 +640,7 @@ void caspar_default_solve_opts(caspar_solve_opts* o) {
   o->min_cost = 1e-30;
   o->pcg_check_every = 4;
   o->flags = 0;
+  o->pred_tol = 0.0;
 }
 
 size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int mode) {
@@ -685,6 +687,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->cam_s = ws + plan.cam_s.off;
     h->cam_trial_s = ws + plan.cam_trial_s.off;
     h->pts_s = ws + plan.pts_s.off;
+    h->wts = ws + plan.wts.off;
     h->X = (double*)(ws + plan.X.off);
     h->X_trial = (double*)(ws + plan.X_trial.off);
     h->cam_c2i = (int*)(ws + plan.cam_c2i.off);
@@ -756,6 +759,18 @@ int caspar_ba_set_params(caspar_ba* h, const double* cams, const double* points)
   if (points) upload_points(h, points, h->X);
   h->linearized = false;
   sync(h);
+  CBA_API_END
+}
+
+int caspar_ba_set_loss(caspar_ba* h, int32_t kind, double scale) {
+  CBA_API_BEGIN
+  CBA_REQUIRE(h != nullptr, "handle is NULL");
+  CBA_REQUIRE(kind == CASPAR_LOSS_TRIVIAL || kind == CASPAR_LOSS_HUBER || kind == CASPAR_LOSS_CAUCHY,
+              "unknown loss kind");
+  CBA_REQUIRE(std::isfinite(scale) && scale > 0.0, "loss scale must be finite and > 0");
+  h->loss = kind;
+  h->loss_c = scale;
+  h->linearized = false;
   CBA_API_END
 }
 

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
                                                     S* __restrict__ g, S* __restrict__ D,
                                                     double* __restrict__ Hpp,
                                                     double* __restrict__ split_rows, int nc,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, int loss, double loss_c,
+                                                    S* __restrict__ wts) {
   __shared__ double red[4];
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform tile index: descriptors come through the scalar cache
@@ -65,8 +66,23 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
     if (act) {
       S r0, r1, col[12][2];
       snavely_jacobian<S>(c, Xp[0], Xp[1], Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+      if (loss == CASPAR_LOSS_TRIVIAL) {
+        cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
+      } else {
+        // robust loss: cost rho(s); residual and blocks scaled by sqrt(rho'(s))
+        double w;
+        cost += robust_rho(loss, loss_c, fma((double)r0, (double)r0, (double)r1 * (double)r1), w);
+        const S sw = (S)sqrt(w);
+        r0 *= sw;
+        r1 *= sw;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          col[j][0] *= sw;
+          col[j][1] *= sw;
+        }
+        wts[o] = (S)w;
+      }
       if (STORE_J) JStore<S>::store(J, o, col);
-      cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
       double jp[3][2];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -183,7 +199,7 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
                                                   const double* __restrict__ cm_px,
                                                   const double* __restrict__ cam,
                                                   const S* __restrict__ pts,
-                                                  double* __restrict__ rows) {
+                                                  double* __restrict__ rows, int loss, double loss_c) {
   __shared__ double lds[4][kCamRowWidth];
   const Chunk ch = chunks[blockIdx.x];
   const Cam<S> c = load_cam<S>(cam, ch.cam);
@@ -196,6 +212,19 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
     const double2 q = reinterpret_cast<const double2*>(cm_px)[j];
     S r0, r1, col[12][2];
     snavely_jacobian<S>(c, xp[0], xp[1], xp[2], (S)q.x, (S)q.y, r0, r1, col);
+    if (loss != CASPAR_LOSS_TRIVIAL) {
+      // the same weight as the point side computes for this observation
+      double w;
+      (void)robust_rho(loss, loss_c, fma((double)r0, (double)r0, (double)r1 * (double)r1), w);
+      const S sw = (S)sqrt(w);
+      r0 *= sw;
+      r1 *= sw;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        col[j][0] *= sw;
+        col[j][1] *= sw;
+      }
+    }
     double jc[9][2];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -267,7 +296,7 @@ __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restric
                                               const double* __restrict__ px,
                                               const S* __restrict__ camtab,
                                               const double* __restrict__ X,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, int loss, double loss_c) {
   __shared__ double red[4];
   const int lane = threadIdx.x & (kWave - 1);
   // wave-uniform tile index: descriptors come through the scalar cache
@@ -296,11 +325,17 @@ __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restric
     const double2 qa = reinterpret_cast<const double2*>(px)[oa];
     const double2 qb = reinterpret_cast<const double2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
+    // rho(|r|^2) of one observation (|r|^2 with the trivial loss)
+    auto term = [&](S r0, S r1) {
+      const double sq = fma((double)r0, (double)r0, (double)r1 * (double)r1);
+      double w;
+      return loss == CASPAR_LOSS_TRIVIAL ? sq : robust_rho(loss, loss_c, sq, w);
+    };
     S r0, r1;
     snavely_residual<S>(ca, (S)xa[0], (S)xa[1], (S)xa[2], (S)qa.x, (S)qa.y, r0, r1);
-    if (lane < na) cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
+    if (lane < na) cost += term(r0, r1);
     snavely_residual<S>(cb, (S)xb[0], (S)xb[1], (S)xb[2], (S)qb.x, (S)qb.y, r0, r1);
-    if (lane < nb) cost += fma((double)r0, (double)r0, (double)r1 * (double)r1);
+    if (lane < nb) cost += term(r0, r1);
   }
   const double tot = block_sum(cost, red);
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
@@ -341,7 +376,8 @@ template <typename S, bool RJ>
 __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
                              const double* __restrict__ px, const double* __restrict__ cam,
                              const double* __restrict__ X, const void* J, const S* __restrict__ cam_s,
-                             const int* __restrict__ s2c, double* resid, double* jc, double* jp) {
+                             const S* __restrict__ wts, const int* __restrict__ s2c, double* resid, double* jc,
+                             double* jp) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (t >= n_tiles) return;
@@ -352,17 +388,25 @@ __global__ void k_export_lin(int n_tiles, const Tile* __restrict__ tiles, const 
   const int ci = (int)(m & ((1u << kCamBits) - 1));
   const int pi = tl.pt_begin + (int)(m >> kCamBits);
   const size_t c = (size_t)s2c[o];
+  // robust loss: the sqrt(w)-scaled residual and blocks (stored blocks are
+  // stored scaled already)
+  const double sw = wts ? sqrt((double)wts[o]) : 1.0;
   if (resid) {
     const Cam<S> cm = load_cam<S>(cam, ci);
     const double* Xp = X + 3 * (size_t)pi;
     const double2 q = reinterpret_cast<const double2*>(px)[o];
     S r0, r1;
     snavely_residual<S>(cm, (S)Xp[0], (S)Xp[1], (S)Xp[2], (S)q.x, (S)q.y, r0, r1);
-    resid[2 * c] = r0;
-    resid[2 * c + 1] = r1;
+    resid[2 * c] = wts ? (double)(r0 * (S)sw) : (double)r0;
+    resid[2 * c + 1] = wts ? (double)(r1 * (S)sw) : (double)r1;
   }
   S col[12][2];
   jacobian_of<S, RJ>(J, cam_s, X, o, ci, pi, col);
+  if (RJ && wts)
+    for (int j = 0; j < 12; ++j) {
+      col[j][0] *= (S)sw;
+      col[j][1] *= (S)sw;
+    }
   if (jc)
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 9; ++j) jc[18 * c + 9 * i + j] = col[j][i];
@@ -416,10 +460,12 @@ static void linearize_t(caspar_ba* h) {
   if (h->n_tiles > 0) {
     if (h->rj)
       k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
-                                                 h->Hpp, h->split_rows, h->nc, h->partials);
+                                                 h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
+                                                 (S*)h->wts);
     else
       k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
-                                                h->Hpp, h->split_rows, h->nc, h->partials);
+                                                h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
+                                                 (S*)h->wts);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
     CBA_LAUNCHED();
@@ -436,7 +482,8 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->n_chunks > 0) {
-    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, ptab, h->chunk_rows);
+    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, ptab, h->chunk_rows,
+                                               h->loss, h->loss_c);
     CBA_LAUNCHED();
   }
   if (h->nc > 0) {
@@ -463,7 +510,8 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
   const bool f64 = fp64 || h->prec == CASPAR_FP64;
   const unsigned tg = f64 ? tile_grid<k_cost<double>>(h->n_tiles) : tile_grid<k_cost<float>>(h->n_tiles);
   if (f64) {
-    k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials);
+    k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials, h->loss,
+                                       h->loss_c);
   } else {
     // float32 rows of the cameras being evaluated, so the residual kernel
     // gathers 64 bytes per observation instead of 128
@@ -471,7 +519,7 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
                                                                               (float*)h->cam_trial_s);
     CBA_LAUNCHED();
     k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, (const float*)h->cam_trial_s, X,
-                                      h->partials);
+                                      h->partials, h->loss, h->loss_c);
   }
   CBA_LAUNCHED();
   k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 1);
@@ -505,7 +553,7 @@ void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* j
   const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
 #define CBA_EXPORT(S, RJ)                                                                                 \
   k_export_lin<S, RJ><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->px, h->cam, h->X, h->J, \
-                                                   (const S*)h->cam_s, h->obs_s2c, resid, jc, jp)
+                                                   (const S*)h->cam_s, weights_of<S>(h), h->obs_s2c, resid, jc, jp)
   if (h->prec == CASPAR_FP64) {
     if (h->rj)
       CBA_EXPORT(double, true);

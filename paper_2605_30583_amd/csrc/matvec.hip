@@ -153,7 +153,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows,
     double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base,
-    unsigned w_pt_bytes, unsigned cold_bytes) {
+    unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
   constexpr int THREADS = MvCfg<S, RJ>::threads;
   constexpr int WAVES = THREADS / kWave;
   constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
@@ -214,11 +214,14 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       S pcv[CamPad<S>::n];      // camera row of p
       Cam<S> cpar;              // camera parameters (recomputed blocks)
       S xj[3];                  // the point (recomputed blocks)
+      S wgt;                    // IRLS weight (recomputed blocks, robust loss)
     };
     // the requests made one tile ahead (tile descriptor T, nt observations,
     // meta word mm of this lane)
     auto request = [&](Regs& R, const Tile& T, int nt, uint32_t mm) {
       if (PREFETCH_J && !RJ) JStore<S>::load(J, T.obs_begin + olane(nt), R.col);
+      // stored blocks are stored sqrt(w)-scaled; recomputed ones take w here
+      if (RJ && wts != nullptr) R.wgt = wts[T.obs_begin + olane(nt)];
       if (PF_PT) {
         const size_t b = 3 * (size_t)(T.pt_begin + (int)(mm >> kCamBits));
 #pragma unroll
@@ -299,7 +302,15 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
           q0 = fma(col[9 + k][0], cur.pjv[k], q0);
           q1 = fma(col[9 + k][1], cur.pjv[k], q1);
         }
-        pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
+        if (RJ && wts != nullptr) {
+          // robust loss: J^T W J p with the observation's weight
+          const double wq = (double)cur.wgt;
+          pap = fma(wq * (double)q0, (double)q0, fma(wq * (double)q1, (double)q1, pap));
+          q0 *= cur.wgt;
+          q1 *= cur.wgt;
+        } else {
+          pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
+        }
 #pragma unroll
         for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
 #pragma unroll
@@ -510,7 +521,8 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
                                      h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows, h->win_rows,
                                      h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,
                                      (unsigned)(3 * (size_t)h->np * sizeof(S)),
-                                     (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)));
+                                     (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)),
+                                     RJ ? weights_of<S>(h) : nullptr);
   CBA_LAUNCHED();
   timing_mark_stop(h);
 }

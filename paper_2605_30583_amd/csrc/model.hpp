@@ -15,6 +15,29 @@ struct Cam {
   T f, k1, k2;
 };
 
+// Robust loss of the squared residual norm s with scale c: returns rho(s)
+// and sets w = rho'(s), the IRLS weight.  kind: CASPAR_LOSS_TRIVIAL (rho = s),
+// CASPAR_LOSS_HUBER (s inside c^2, 2 c sqrt(s) - c^2 outside),
+// CASPAR_LOSS_CAUCHY (c^2 log(1 + s / c^2)).
+__device__ inline double robust_rho(int kind, double c, double s, double& w) {
+  const double c2 = c * c;
+  if (kind == CASPAR_LOSS_HUBER) {
+    if (s <= c2) {
+      w = 1.0;
+      return s;
+    }
+    const double rs = sqrt(s);
+    w = c / rs;
+    return 2.0 * c * rs - c2;
+  }
+  if (kind == CASPAR_LOSS_CAUCHY) {
+    w = 1.0 / (1.0 + s / c2);
+    return c2 * log1p(s / c2);
+  }
+  w = 1.0;
+  return s;
+}
+
 // Point coordinates in the working precision: float32 rows (x, y, z, 0) read
 // with one 16-byte load, or the float64 master rows of 3.
 template <typename S>

@@ -129,7 +129,7 @@ template <typename S, bool RJ>
 __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
                               const void* __restrict__ J, const S* __restrict__ cam_s,
                               const double* __restrict__ X, const S* __restrict__ v, int nc,
-                              const int* __restrict__ s2c, double* __restrict__ out) {
+                              const int* __restrict__ s2c, const S* __restrict__ wts, double* __restrict__ out) {
   const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (t >= n_tiles) return;
@@ -151,6 +151,13 @@ __global__ void k_adjoint_obs(int n_tiles, const Tile* __restrict__ tiles, const
     const double x = v[9 * (size_t)nc + 3 * (size_t)pi + k];
     q0 = fma((double)col[9 + k][0], x, q0);
     q1 = fma((double)col[9 + k][1], x, q1);
+  }
+  // robust loss (weights held fixed): dL/dpx_o = w_o J_o v; stored blocks
+  // are sqrt(w)-scaled, recomputed ones are not
+  if (wts) {
+    const double f = RJ ? (double)wts[o] : sqrt((double)wts[o]);
+    q0 *= f;
+    q1 *= f;
   }
   const size_t c = (size_t)s2c[o];
   out[2 * c] = q0;
@@ -179,6 +186,7 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
   CBA_REQUIRE(o.max_lm_iters >= 0 && o.max_pcg_iters >= 0, "negative iteration limit");
   CBA_REQUIRE(o.lambda0 > 0.0 && o.lambda_min > 0.0 && o.lambda_max >= o.lambda_min, "bad damping options");
   CBA_REQUIRE(o.pcg_tol >= 0.0, "bad PCG tolerance");
+  CBA_REQUIRE(o.pred_tol >= 0.0, "bad predicted-decrease tolerance");
   const auto t_start = std::chrono::steady_clock::now();
   ensure_linearized(h);
   if (!std::isfinite(h->cost)) fail(CASPAR_ENUMERIC, "initial cost is not finite");
@@ -203,6 +211,11 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
     double gx, xr, xDx;
     run_pred_dots(h, &gx, &xr, &xDx);
     const double pred = 0.5 * (-gx + xr + lam * xDx);
+    if (o.pred_tol > 0.0 && pred <= o.pred_tol * h->cost) {
+      // the model predicts no decrease the cost could resolve
+      reason = 3;
+      break;
+    }
     run_retract(h, h->vec.x);
     const double Ft = run_cost(h, h->cam_trial, h->X_trial, false);
     const double F = h->cost;
@@ -215,6 +228,11 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
       std::swap(h->X, h->X_trial);
       h->linearized = false;
       run_linearize(h);
+      // the cost of the new parameters is the trial cost the step was
+      // accepted on (the linearisation's own sum differs in rounding order),
+      // so accepted costs decrease exactly and the next gain ratio compares
+      // like with like
+      h->cost = Ft;
       lam *= std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * rho - 1.0, 3));
       nu = 2.0;
       ++accepted;
@@ -263,10 +281,12 @@ static void adjoint_obs_t(caspar_ba* h, double* out) {
   const unsigned grid = nblk((int64_t)h->n_tiles * kWave, 256);
   if (h->rj)
     k_adjoint_obs<S, true><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->cam_s,
-                                                        h->X, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+                                                        h->X, (const S*)h->vec.x, h->nc, h->obs_s2c,
+                                                        weights_of<S>(h), out);
   else
     k_adjoint_obs<S, false><<<grid, 256, 0, h->stream>>>(h->n_tiles, h->tiles, h->meta, h->J, (const S*)h->cam_s,
-                                                         h->X, (const S*)h->vec.x, h->nc, h->obs_s2c, out);
+                                                         h->X, (const S*)h->vec.x, h->nc, h->obs_s2c,
+                                                        weights_of<S>(h), out);
   CBA_LAUNCHED();
 }
 

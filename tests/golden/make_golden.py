@@ -25,8 +25,8 @@ RUNS = {
     "tiny": ("tiny", 20, "trivial", 1.0),
     "medium": ("medium", 30, "trivial", 1.0),
     "bal1700": ("bal1700", 20, "trivial", 1.0),
-    "tiny_outliers_huber": ("tiny_outliers", 20, "huber", 3.0),
-    "tiny_outliers_cauchy": ("tiny_outliers", 20, "cauchy", 3.0),
+    "tiny_outliers_huber": ("tiny_outliers", 40, "huber", 3.0),
+    "tiny_outliers_cauchy": ("tiny_outliers", 40, "cauchy", 3.0),
 }
 
 

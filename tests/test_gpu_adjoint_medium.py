@@ -55,8 +55,12 @@ def test_medium_adjoint_matches_full_resolve_differences(noise, tol):
     obs = rng.choice(sc.n_obs, 50, replace=False)
     coord = rng.integers(0, 2, size=50)
     h = 1e-4
-    opts = SolveOptions(max_lm_iters=8, pcg_tol=1e-12, max_pcg_iters=5000, lambda0=1e-8, grad_tol=0.0,
-                        min_cost=0.0)
+    # once converged, steps predict decreases far below the resolution of the
+    # cost and their gain ratio is rounding noise; accepting such steps by
+    # chance moves the gauge and with it L, so the re-solves stop at the
+    # cost's resolution (pred <= 4 DBL_EPSILON F)
+    opts = SolveOptions(max_lm_iters=20, pcg_tol=1e-12, max_pcg_iters=5000, lambda0=1e-8, grad_tol=0.0,
+                        min_cost=0.0, pred_tol=4 * np.finfo(np.float64).eps)
     px_t = t64(px)
     fd = np.empty(50)
     for i, (o, c) in enumerate(zip(obs, coord)):
@@ -73,5 +77,7 @@ def test_medium_adjoint_matches_full_resolve_differences(noise, tol):
     ad = grad[obs, coord]
     scale = np.abs(grad).max()
     err = np.abs(fd - ad).max() / scale
-    print(f"noise {noise}: max |fd - adjoint| / max|grad| = {err:.3e}")
+    worst = int(np.argmax(np.abs(fd - ad)))
+    print(f"noise {noise}: max |fd - adjoint| / max|grad| = {err:.3e} (sample {worst}: fd {fd[worst]:.6e}, "
+          f"adjoint {ad[worst]:.6e}; median error {np.median(np.abs(fd - ad)) / scale:.3e})")
     assert err <= tol

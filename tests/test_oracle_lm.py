@@ -91,3 +91,21 @@ def test_independent_least_squares_reaches_the_same_cost():
         tr_options={"atol": 1e-14, "btol": 1e-14},
         args=(nc, npnt, sc.obs_cam, sc.obs_pt, px))
     assert abs(out.cost - res.final_cost) <= 1e-9 * res.final_cost, (out.cost, res.final_cost)
+
+
+def test_predicted_decrease_stop_ends_at_the_cost_resolution():
+    """pred_tol: once the step's predicted decrease is below a few DBL_EPSILON
+    of F, the gain ratio is rounding noise; the solve stops there with the
+    converged cost."""
+    from oracle import camera as cam_mod
+    sc = small_scene(n_cams=6, n_points=200, seed=11, k=4)
+    px = observed_pixels(sc)
+    st = cam_mod.State.from_bal(sc.cams_init, sc.points_init)
+    full = lm.solve(st, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=30, inner="schur"))
+    tol = 4 * np.finfo(np.float64).eps
+    stop = lm.solve(st, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=30, inner="schur", pred_tol=tol))
+    assert stop.stop_reason == "pred"
+    assert len(stop.history) < len(full.history)
+    assert all(h.pred > tol * h_prev for h, h_prev in
+               zip(stop.history, [stop.initial_cost] + [h.cost for h in stop.history]))
+    assert abs(stop.final_cost - full.final_cost) <= 1e-12 * full.final_cost
