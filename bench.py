@@ -10,7 +10,8 @@ values), then the parameters are reset and exactly K iterations are timed
 (early stopping off), with inputs resident in HBM.
 
 The headline recomputes the Jacobian blocks inside every normal-equation
-product (--jacobian recompute); the run with stored blocks follows it.
+product (--jacobian recompute); the run with stored blocks follows it, then
+the same solve with a Huber loss (robust re-weighting, scale 3 px).
 
 Printed: one JSON line with LM iterations/s (value), the roofline of the
 fused product (its average duration measured with HIP events on the
@@ -62,6 +63,8 @@ def parse():
                     help="skip the run with the other Jacobian handling beside the headline one")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 plain solve beside the mixed one")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-robust", action="store_true", help="skip the Huber-loss solve beside the headline")
+    ap.add_argument("--robust-scale", type=float, default=3.0, help="Huber scale in pixels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-points", type=int, default=150_000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -158,9 +161,11 @@ def main():
     cams0, pts0 = t64(sc.cams_init), t64(sc.points_init)
     prec = FP32_MIXED if a.precision == "fp32_mixed" else FP64
 
-    def timed_solve(precision, label, jacobian=a.jacobian):
+    def timed_solve(precision, label, jacobian=a.jacobian, loss=None):
         t = time.time()
         ba = BundleAdjuster(cams0, pts0, oc, op, px, precision, recompute_jacobian=(jacobian == "recompute"))
+        if loss is not None:
+            ba.set_loss(*loss)
         torch.cuda.synchronize()
         log(f"{label}: create {time.time() - t:.2f}s, layout {ba.layout_info()}")
         if a.warmup > 0:
@@ -220,6 +225,20 @@ def main():
             "matvec_tflops": FLOPS_PER_OBS[alt] * sc.n_obs / (mv_alt * 1e-3) / 1e12,
         }
         del ba_alt
+        torch.cuda.empty_cache()
+
+    if not a.no_robust:
+        ba_r, st_r, dt_r, tim_r = timed_solve(prec, f"{a.precision}/huber", loss=("huber", a.robust_scale))
+        mv_r = tim_r["matvec_ms"] / max(1, tim_r["matvec_launches"])
+        extra["huber_loss"] = {
+            "scale_px": a.robust_scale,
+            "lm_iters_per_s": st_r["lm_iters"] / dt_r,
+            "ms_per_step": 1e3 * dt_r / max(1, st_r["lm_iters"]),
+            "pcg_iters_total": st_r["pcg_iters_total"],
+            "matvec_avg_ms": mv_r,
+            "final_robust_cost_fp64_eval": ba_r.cost_fp64(),
+        }
+        del ba_r
         torch.cuda.empty_cache()
 
     if not a.no_adjoint:
