@@ -285,36 +285,34 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 #pragma unroll
       for (int k = 0; k < 3; ++k) yp[k] = (S)0;
       if (act) {
-        S rcol[12][2];
-        S(&col)[12][2] = RJ ? rcol : cur.col;
-        if (RJ) {
-          S r0, r1;
-          snavely_jacobian<S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], (S)0, (S)0, r0, r1, rcol);
-        }
-        S q0 = (S)0, q1 = (S)0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          q0 = fma(col[k][0], cur.pcv[k], q0);
-          q1 = fma(col[k][1], cur.pcv[k], q1);
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          q0 = fma(col[9 + k][0], cur.pjv[k], q0);
-          q1 = fma(col[9 + k][1], cur.pjv[k], q1);
-        }
-        if (RJ && wts != nullptr) {
-          // robust loss: J^T W J p with the observation's weight
-          const double wq = (double)cur.wgt;
-          pap = fma(wq * (double)q0, (double)q0, fma(wq * (double)q1, (double)q1, pap));
-          q0 *= cur.wgt;
-          q1 *= cur.wgt;
+        if constexpr (RJ) {
+          // blocks applied in factored form from the camera and the point;
+          // a robust loss weights q (J^T W J p)
+          const S qwq = wts != nullptr
+                            ? snavely_apply<true, S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], cur.pcv,
+                                                     cur.pjv, cur.wgt, yc, yp)
+                            : snavely_apply<false, S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], cur.pcv,
+                                                      cur.pjv, (S)1, yc, yp);
+          pap += (double)qwq;
         } else {
+          const S(&col)[12][2] = cur.col;
+          S q0 = (S)0, q1 = (S)0;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            q0 = fma(col[k][0], cur.pcv[k], q0);
+            q1 = fma(col[k][1], cur.pcv[k], q1);
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            q0 = fma(col[9 + k][0], cur.pjv[k], q0);
+            q1 = fma(col[9 + k][1], cur.pjv[k], q1);
+          }
           pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
+#pragma unroll
+          for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
         }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
         // LDS sums: the most observed cameras into their private copies,
         // the other hot cameras, and the cold cameras of this workgroup's
         // window
@@ -350,9 +348,10 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       const bool split = tile_split(tl.info);
       // lambda p^T D p, once per point
       if (head && (!split || tile_first(tl.info))) {
+        S dpp = (S)0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          pap = fma(lambda * (double)cur.dpv[k] * (double)cur.pjv[k], (double)cur.pjv[k], pap);
+        for (int k = 0; k < 3; ++k) dpp = fma(cur.dpv[k] * cur.pjv[k], cur.pjv[k], dpp);
+        pap = fma(lambda, (double)dpp, pap);
       }
       // the point rows of w (ordinary tiles)
       {
@@ -412,11 +411,13 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 // Camera rows of w, split and orphan points, p^T A p and (in PCG) alpha.
 // Block roles by index:
 //   [0, nb_hot):           column sums of the per-workgroup rows of the LDS
-//                          cameras (64 columns x 4 row groups per block);
+//                          cameras (16 columns x 16 row groups per block);
 //   [nb_hot, +nb_cold):    one wave per remaining camera, lanes striding its
 //                          observation rows;
 //   the rest:              split points and points without observations.
 // Block 0 also turns the p^T A p partials into pAp (and alpha in PCG).
+constexpr int kHotCols = 16;  // hot-sum columns per final-kernel workgroup
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_matvec_final(
     int nc, int K, int G, const double* __restrict__ hot_rows,
@@ -426,23 +427,34 @@ __global__ __launch_bounds__(256) void k_matvec_final(
     S* __restrict__ w, int n_split, const SplitPoint* __restrict__ sp, const double* __restrict__ split_rows,
     int n_orphan, const double* __restrict__ partials, DevScalars* __restrict__ sc, int pcg_mode, int nb_hot,
     int nb_cold) {
-  using A = double;
   __shared__ double red[4][64];
   if (pcg_mode && sc->done) return;
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
   const int b = blockIdx.x;
   if (b < nb_hot) {
+    // kHotCols consecutive columns (one 128-byte line per row) x 16 row
+    // groups; each thread sums every 16th workgroup row with two independent
+    // accumulators, then the 16 group sums are added in LDS
+    double (*gsum)[kHotCols] = reinterpret_cast<double (*)[kHotCols]>(&red[0][0]);
     const int ncol = K * 9;
-    const int col = b * 64 + lane;
-    double s = 0.0;
+    const int cl = tid % kHotCols, gr = tid / kHotCols;
+    const int col = b * kHotCols + cl;
+    double s0 = 0.0, s1 = 0.0;
     if (col < ncol) {
-      const A* r = hot_rows + col;
-      for (int g = grp; g < G; g += 4) s += (double)r[(size_t)g * ncol];
+      const double* r = hot_rows + col;
+      int g = gr;
+      for (; g + 16 < G; g += 32) {
+        s0 += r[(size_t)g * ncol];
+        s1 += r[(size_t)(g + 16) * ncol];
+      }
+      if (g < G) s0 += r[(size_t)g * ncol];
     }
-    red[grp][lane] = s;
+    gsum[gr][cl] = s0 + s1;
     __syncthreads();
-    if (grp == 0 && col < ncol) {
-      const double tot = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    if (gr == 0 && col < ncol) {
+      double tot = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) tot += gsum[k][cl];
       w[col] = (S)fma(lambda * (double)D[col], (double)p[col], tot);
     }
   } else if (b < nb_hot + nb_cold) {
@@ -541,7 +553,7 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
     else
       launch_matvec<S, false>(h, lambda, p, w, scp);
   }
-  const int nb_hot = (h->K * 9 + 63) / 64;
+  const int nb_hot = (h->K * 9 + kHotCols - 1) / kHotCols;
   const int nb_cold = (h->nc - h->K + 3) / 4;
   const int64_t nrest = 3 * (int64_t)h->n_split_pts + 3 * (int64_t)h->n_orphan_pts;
   const int nb_rest = (int)((nrest + 255) / 256);

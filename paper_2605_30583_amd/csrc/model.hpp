@@ -193,6 +193,73 @@ __device__ inline void snavely_jacobian(const Cam<T>& c, T X0, T X1, T X2, T px0
   }
 }
 
+// 1/d for the projection: the hardware reciprocal in float32 (within one ulp,
+// below the rounding of the float32 products that use it), exact division in
+// float64.
+__device__ inline float proj_recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ inline double proj_recip(double d) { return 1.0 / d; }
+
+// One observation's share of the normal-equation product, from the camera
+// and the point, without forming its blocks.  With the block structure
+// above (J_t = B, J_X = B R, row i of J_w = X x row i of J_X):
+//   q        = J_c p_c + J_X p_X
+//            = B (R (p_X + p_w x X) + p_t) + p (radial p_f + f |p|^2 (p_k1 + |p|^2 p_k2)),
+// and with q~ = wgt q (the IRLS weight, 1 without a robust loss)
+//   J_t^T q~ = B^T q~,   J_X^T q~ = R^T B^T q~,   J_w^T q~ = X x (J_X^T q~),
+//   J_f,k1,k2^T q~ = (radial, f |p|^2, f |p|^4) (p . q~).
+// pc holds the camera tangent [dw, dt, df, dk1, dk2]; returns q . q~ (the
+// observation's term of p^T J^T W J p), yc (9) and yp (3) are J_c^T q~ and
+// J_X^T q~.  WEIGHTED = false skips the weight (wgt is then ignored).
+template <bool WEIGHTED, typename T>
+__device__ inline T snavely_apply(const Cam<T>& c, T X0, T X1, T X2, const T* pc, const T pp[3], T wgt,
+                                  T yc[9], T yp[3]) {
+  const T P0 = fma(c.R[0], X0, fma(c.R[1], X1, fma(c.R[2], X2, c.t[0])));
+  const T P1 = fma(c.R[3], X0, fma(c.R[4], X1, fma(c.R[5], X2, c.t[1])));
+  const T P2 = fma(c.R[6], X0, fma(c.R[7], X1, fma(c.R[8], X2, c.t[2])));
+  const T d = P2 + (P2 >= (T)0 ? Scalar<T>::eps() : -Scalar<T>::eps());
+  const T m = -proj_recip(d);
+  const T p0 = P0 * m, p1 = P1 * m;
+  const T n2 = fma(p0, p0, p1 * p1);
+  const T rad = fma(n2, fma(c.k2, n2, c.k1), (T)1);
+  const T fr = c.f * rad;
+  const T fs = c.f * (T)2 * fma((T)2 * c.k2, n2, c.k1);
+  // B = m [A | A p], A = fr I + fs p p^T
+  const T fp0 = fs * p0, fp1 = fs * p1;
+  const T B00 = m * fma(fp0, p0, fr), B01 = m * (fp0 * p1), B11 = m * fma(fp1, p1, fr);
+  const T B02 = fma(B00, p0, B01 * p1);
+  const T B12 = fma(B01, p0, B11 * p1);
+  // v = R (p_X + p_w x X) + p_t
+  const T u0 = fma(pc[1], X2, fma(-pc[2], X1, pp[0]));
+  const T u1 = fma(pc[2], X0, fma(-pc[0], X2, pp[1]));
+  const T u2 = fma(pc[0], X1, fma(-pc[1], X0, pp[2]));
+  const T v0 = fma(c.R[0], u0, fma(c.R[1], u1, fma(c.R[2], u2, pc[3])));
+  const T v1 = fma(c.R[3], u0, fma(c.R[4], u1, fma(c.R[5], u2, pc[4])));
+  const T v2 = fma(c.R[6], u0, fma(c.R[7], u1, fma(c.R[8], u2, pc[5])));
+  const T fn2 = c.f * n2;
+  const T s = fma(rad, pc[6], fn2 * fma(n2, pc[8], pc[7]));
+  const T q0 = fma(B00, v0, fma(B01, v1, fma(B02, v2, p0 * s)));
+  const T q1 = fma(B01, v0, fma(B11, v1, fma(B12, v2, p1 * s)));
+  const T w0 = WEIGHTED ? wgt * q0 : q0, w1 = WEIGHTED ? wgt * q1 : q1;
+  // transposes
+  const T g0 = fma(B00, w0, B01 * w1);
+  const T g1 = fma(B01, w0, B11 * w1);
+  const T g2 = fma(B02, w0, B12 * w1);
+  yp[0] = fma(c.R[0], g0, fma(c.R[3], g1, c.R[6] * g2));
+  yp[1] = fma(c.R[1], g0, fma(c.R[4], g1, c.R[7] * g2));
+  yp[2] = fma(c.R[2], g0, fma(c.R[5], g1, c.R[8] * g2));
+  yc[0] = fma(X1, yp[2], -X2 * yp[1]);
+  yc[1] = fma(X2, yp[0], -X0 * yp[2]);
+  yc[2] = fma(X0, yp[1], -X1 * yp[0]);
+  yc[3] = g0;
+  yc[4] = g1;
+  yc[5] = g2;
+  const T h = fma(p0, w0, p1 * w1);
+  yc[6] = rad * h;
+  yc[7] = fn2 * h;
+  yc[8] = fn2 * n2 * h;
+  return fma(w0, q0, w1 * q1);
+}
+
 // Exp of an angle-axis vector (Rodrigues), row-major 3x3.
 // R = I + s [w]x + c [w]x^2 with s = sin(a)/a, c = (1 - cos a)/a^2;
 // series below a = 1e-4.
