@@ -75,6 +75,12 @@ struct ColdRow<float> {
   static constexpr int n = 12;
 };
 
+// Camera rows of the recomputed-block product: the rotation as a unit
+// quaternion (w, x, y, z), t, f, k1, k2, then the camera's 9 values of the
+// product's input p and one pad (80 bytes in float32, 160 in float64).
+constexpr int kProdCamRow = 20;
+constexpr int kProdCamP = 10;  // offset of p in the row
+
 template <typename S>
 struct CamPad;
 template <>
@@ -202,7 +208,8 @@ struct caspar_ba {
 
   // fused product side buffers
   int* cold_lo = nullptr;       // [G] first camera of each product workgroup's LDS window
-  void* p_cam = nullptr;        // [nc][kCamPad] camera part of the product's input, 16-byte rows
+  void* p_cam = nullptr;        // camera rows of the product's input: [nc][CamPad] (stored blocks) or
+                                // [nc][kProdCamRow] with the camera parameters (recomputed blocks)
   int* cold_list = nullptr;     // cold rows grouped by camera
   int* cold_off = nullptr;      // [nc - K + 1]
   void* cold_rows = nullptr;    // [cold_local_base][ColdRow<S>::n] rows of single cold observations
@@ -260,6 +267,14 @@ template <typename S>
 inline const S* weights_of(const caspar_ba* h) {
   return h->loss == CASPAR_LOSS_TRIVIAL ? nullptr : static_cast<const S*>(h->wts);
 }
+
+// Layout of the product's camera rows of p: stride of a row and offset of
+// the camera's 9 values in it.
+template <typename S>
+inline int cam_row_stride(const caspar_ba* h) {
+  return h->rj ? kProdCamRow : CamPad<S>::n;
+}
+inline int cam_row_p_off(const caspar_ba* h) { return h->rj ? kProdCamP : 0; }
 
 // Points in the working precision: the float32 copy written at each
 // linearisation, or the (current) float64 master rows.

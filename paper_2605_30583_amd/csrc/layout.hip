@@ -111,7 +111,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.J, std::max(rj ? 0 : nch * no_pad * 16, scratch));
   take(p.tiles, p.max_tiles * sizeof(Tile));
   take(p.cold_lo, (size_t)kMaxGroups * 4);
-  take(p.p_cam, (size_t)nc * 80);  // 10 doubles or 12 floats per camera
+  take(p.p_cam, (size_t)nc * kProdCamRow * 8);
   take(p.cm_pt, (size_t)no * 4);
   take(p.cm_px, (size_t)no * 16);
   take(p.cam_off, ((size_t)nc + 1) * 4);

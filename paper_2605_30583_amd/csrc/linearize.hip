@@ -28,6 +28,54 @@ __global__ void k_cam_cast(int n, const double* __restrict__ cam, S* __restrict_
   if (i < n) out[i] = (S)cam[i];
 }
 
+// Camera parameters of the recomputed-block product's rows (the first
+// kProdCamP values; the product's input fills the rest).  The unit quaternion
+// of R is taken with the largest of the four pivots 1 + tr R, 1 + 2 R_ii - tr R
+// (Shepperd's method), which keeps the division away from zero, and is
+// normalised in float64 before the cast.
+template <typename S>
+__global__ void k_cam_quat(int nc, const double* __restrict__ cam, S* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double* in = cam + (size_t)c * kCamStride;
+  const double r00 = in[0], r01 = in[1], r02 = in[2];
+  const double r10 = in[3], r11 = in[4], r12 = in[5];
+  const double r20 = in[6], r21 = in[7], r22 = in[8];
+  const double tr = r00 + r11 + r22;
+  double q[4];  // w, x, y, z
+  if (tr >= r00 && tr >= r11 && tr >= r22) {
+    const double s = 2.0 * sqrt(1.0 + tr);  // 4 w
+    q[0] = 0.25 * s;
+    q[1] = (r21 - r12) / s;
+    q[2] = (r02 - r20) / s;
+    q[3] = (r10 - r01) / s;
+  } else if (r00 >= r11 && r00 >= r22) {
+    const double s = 2.0 * sqrt(1.0 + r00 - r11 - r22);  // 4 x
+    q[0] = (r21 - r12) / s;
+    q[1] = 0.25 * s;
+    q[2] = (r01 + r10) / s;
+    q[3] = (r02 + r20) / s;
+  } else if (r11 >= r22) {
+    const double s = 2.0 * sqrt(1.0 - r00 + r11 - r22);  // 4 y
+    q[0] = (r02 - r20) / s;
+    q[1] = (r01 + r10) / s;
+    q[2] = 0.25 * s;
+    q[3] = (r12 + r21) / s;
+  } else {
+    const double s = 2.0 * sqrt(1.0 - r00 - r11 + r22);  // 4 z
+    q[0] = (r10 - r01) / s;
+    q[1] = (r02 + r20) / s;
+    q[2] = (r12 + r21) / s;
+    q[3] = 0.25 * s;
+  }
+  const double inv = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  S* o = out + (size_t)c * kProdCamRow;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = (S)(q[k] * inv);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) o[4 + k] = (S)in[9 + k];
+}
+
 // float32 point rows (x, y, z, 0), one 16-byte load each.
 __global__ void k_point_cast(int np, const double* __restrict__ X, float4* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,6 +497,10 @@ static void linearize_t(caspar_ba* h) {
   if (cast && h->nc > 0) {
     k_cam_cast<S><<<nblk((int64_t)h->nc * kCamStride, 256), 256, 0, st>>>(h->nc * kCamStride, h->cam,
                                                                           (S*)h->cam_s);
+    CBA_LAUNCHED();
+  }
+  if (h->rj && h->nc > 0) {
+    k_cam_quat<S><<<nblk(h->nc, 256), 256, 0, st>>>(h->nc, h->cam, (S*)h->p_cam);
     CBA_LAUNCHED();
   }
   const S* camtab = cast ? (const S*)h->cam_s : (const S*)h->cam;

@@ -24,15 +24,17 @@
 
 namespace cba {
 
-// Camera part of p copied to 16-byte aligned rows for vector loads.
+// Camera part of p copied into the 16-byte aligned camera rows the product
+// gathers (row_stride values per camera, p at row_off, zeros to the row's
+// end).
 template <typename S>
-__global__ void k_pad_cams(int nc, const S* __restrict__ p, S* __restrict__ out, const DevScalars* __restrict__ sc) {
+__global__ void k_pad_cams(int nc, const S* __restrict__ p, S* __restrict__ out, int row_stride, int row_off,
+                           const DevScalars* __restrict__ sc) {
   if (sc != nullptr && sc->done) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  S* o = out + (size_t)c * CamPad<S>::n;
-#pragma unroll
-  for (int k = 0; k < CamPad<S>::n; ++k) o[k] = k < 9 ? p[9 * (size_t)c + k] : (S)0;
+  S* o = out + (size_t)c * row_stride + row_off;
+  for (int k = 0; k < row_stride - row_off; ++k) o[k] = k < 9 ? p[9 * (size_t)c + k] : (S)0;
 }
 
 template <typename S>
@@ -68,10 +70,11 @@ __device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c
 //                 no room and loads them at the end of the previous tile);
 //   prefetch_pt:  p and D of the tile's points (otherwise loaded with the
 //                 camera gathers of the tile itself);
-//   prefetch_cam: the camera rows of p and, with recomputed blocks, the
-//                 camera parameters and the point (otherwise gathered at the
-//                 start of the tile, with their latency exposed; float64
-//                 stored blocks would spill).
+//   prefetch_cam: the camera rows (p alone with stored blocks; with
+//                 recomputed blocks one row holds the camera parameters and
+//                 p) and, with recomputed blocks, the point (otherwise
+//                 gathered at the start of the tile, with their latency
+//                 exposed; float64 stored blocks would spill).
 template <typename S, bool RJ>
 struct MvCfg {
   static constexpr int threads = 1024;
@@ -147,7 +150,7 @@ __device__ inline void store3(__amdgpu_buffer_rsrc_t rs, unsigned off, const dou
 template <typename S, bool RJ>
 __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
-    const void* __restrict__ J, const S* __restrict__ cam_s, const S* __restrict__ pts_s,
+    const void* __restrict__ J, const S* __restrict__ pts_s,
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
@@ -159,6 +162,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
   constexpr bool PF_PT = MvCfg<S, RJ>::prefetch_pt;
   constexpr bool PF_CAM = MvCfg<S, RJ>::prefetch_cam;
+  static_assert(PF_CAM || !RJ, "recomputed blocks prefetch their camera rows");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
   // the P most observed cameras get kPrivCopies private copies (copy = lane
@@ -211,8 +215,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     struct Regs {
       S col[12][2];             // Jacobian columns (stored blocks)
       S pjv[3], dpv[3];         // p and D of the observation's point
-      S pcv[CamPad<S>::n];      // camera row of p
-      Cam<S> cpar;              // camera parameters (recomputed blocks)
+      S pcv[CamPad<S>::n];      // camera row of p (stored blocks)
+      S crow[kProdCamRow];      // camera row: parameters and p (recomputed blocks)
       S xj[3];                  // the point (recomputed blocks)
       S wgt;                    // IRLS weight (recomputed blocks, robust loss)
     };
@@ -232,10 +236,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       }
       if (PF_CAM) {
         const int c = (int)(mm & ((1u << kCamBits) - 1));
-        load_cam_row<S>(p_cam, c, R.pcv);
         if (RJ) {
-          R.cpar = load_cam_s<S>(cam_s, c);
+          load_prod_cam<S>(p_cam, c, R.crow);
           load_point<S>(pts_s, (size_t)(T.pt_begin + (int)(mm >> kCamBits)), R.xj);
+        } else {
+          load_cam_row<S>(p_cam, c, R.pcv);
         }
       }
     };
@@ -266,10 +271,6 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
           cur.dpv[k] = dp_base[b + k];
         }
       }
-      if (RJ && !PF_CAM) {
-        cur.cpar = load_cam_s<S>(cam_s, ci_raw);
-        load_point<S>(pts_s, (size_t)(tl.pt_begin + lp_raw), cur.xj);
-      }
       // 2. requests for the next tiles, issued after the gathers so that
       //    waiting for the gathers does not wait for them
       __builtin_amdgcn_sched_barrier(0);
@@ -288,11 +289,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
         if constexpr (RJ) {
           // blocks applied in factored form from the camera and the point;
           // a robust loss weights q (J^T W J p)
+          const Cam<S> cam = prod_cam<S>(cur.crow);
+          const S* pc = cur.crow + kProdCamP;
           const S qwq = wts != nullptr
-                            ? snavely_apply<true, S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], cur.pcv,
-                                                     cur.pjv, cur.wgt, yc, yp)
-                            : snavely_apply<false, S>(cur.cpar, cur.xj[0], cur.xj[1], cur.xj[2], cur.pcv,
-                                                      cur.pjv, (S)1, yc, yp);
+                            ? snavely_apply<true, S>(cam, cur.xj[0], cur.xj[1], cur.xj[2], pc, cur.pjv, cur.wgt, yc, yp)
+                            : snavely_apply<false, S>(cam, cur.xj[0], cur.xj[1], cur.xj[2], pc, cur.pjv, (S)1, yc, yp);
           pap += (double)qwq;
         } else {
           const S(&col)[12][2] = cur.col;
@@ -528,7 +529,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
   if (lds > 65536)
     CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   timing_mark_start(h);
-  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)h->cam_s, (const S*)pts_table(h),
+  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)pts_table(h),
                                      (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
                                      h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows, h->win_rows,
                                      h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,
@@ -545,7 +546,8 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   const DevScalars* scp = pcg_mode ? h->scal : nullptr;
   if (h->n_tiles > 0 || h->nc > 0 || h->n_orphan_pts > 0) {
     if (pad_cams) {
-      k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(h->nc, p, (S*)h->p_cam, scp);
+      k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(
+          h->nc, p, (S*)h->p_cam, cam_row_stride<S>(h), cam_row_p_off(h), scp);
       CBA_LAUNCHED();
     }
     if (h->rj)

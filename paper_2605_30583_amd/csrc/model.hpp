@@ -110,6 +110,61 @@ __device__ inline Cam<float> load_cam_s<float>(const float* __restrict__ tab, in
   return cam;
 }
 
+// One camera row of the recomputed-block product (kProdCamRow values) with
+// 16-byte vector loads.
+template <typename S>
+__device__ inline void load_prod_cam(const S* __restrict__ tab, int c, S (&row)[kProdCamRow]);
+template <>
+__device__ inline void load_prod_cam<float>(const float* __restrict__ tab, int c, float (&row)[kProdCamRow]) {
+  const float4* r = reinterpret_cast<const float4*>(tab + (size_t)c * kProdCamRow);
+#pragma unroll
+  for (int i = 0; i < kProdCamRow / 4; ++i) {
+    const float4 v = r[i];
+    row[4 * i] = v.x;
+    row[4 * i + 1] = v.y;
+    row[4 * i + 2] = v.z;
+    row[4 * i + 3] = v.w;
+  }
+}
+template <>
+__device__ inline void load_prod_cam<double>(const double* __restrict__ tab, int c, double (&row)[kProdCamRow]) {
+  const double2* r = reinterpret_cast<const double2*>(tab + (size_t)c * kProdCamRow);
+#pragma unroll
+  for (int i = 0; i < kProdCamRow / 2; ++i) {
+    const double2 v = r[i];
+    row[2 * i] = v.x;
+    row[2 * i + 1] = v.y;
+  }
+}
+
+// Camera of a product row: R from the unit quaternion (w, x, y, z),
+//   R = I + 2 w [v]x + 2 [v]x^2,  v = (x, y, z).
+template <typename T>
+__device__ inline Cam<T> prod_cam(const T (&row)[kProdCamRow]) {
+  const T w = row[0], x = row[1], y = row[2], z = row[3];
+  const T x2 = x + x, y2 = y + y, z2 = z + z;
+  const T xx = x * x2, yy = y * y2, zz = z * z2;
+  const T xy = x * y2, xz = x * z2, yz = y * z2;
+  const T wx = w * x2, wy = w * y2, wz = w * z2;
+  Cam<T> c;
+  c.R[0] = (T)1 - (yy + zz);
+  c.R[1] = xy - wz;
+  c.R[2] = xz + wy;
+  c.R[3] = xy + wz;
+  c.R[4] = (T)1 - (xx + zz);
+  c.R[5] = yz - wx;
+  c.R[6] = xz - wy;
+  c.R[7] = yz + wx;
+  c.R[8] = (T)1 - (xx + yy);
+  c.t[0] = row[4];
+  c.t[1] = row[5];
+  c.t[2] = row[6];
+  c.f = row[7];
+  c.k1 = row[8];
+  c.k2 = row[9];
+  return c;
+}
+
 // Residual of one observation.  P = R X + t; the depth keeps its sign away
 // from zero (d + eps sign(d), sign(0) = +1); p = -P_xy / d;
 // radial = 1 + k1 |p|^2 + k2 |p|^4; r = f radial p - px.

@@ -306,7 +306,8 @@ __global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevSca
 // product gathers from.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_p(int64_t N, int nc, const S* __restrict__ z, S* __restrict__ p,
-                                               S* __restrict__ p_cam, const DevScalars* __restrict__ sc) {
+                                               S* __restrict__ p_cam, int row_stride, int row_off,
+                                               const DevScalars* __restrict__ sc) {
   using V = S __attribute__((ext_vector_type(4)));
   if (sc->done) return;
   const double beta = sc->beta;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void k_pcg_p(int64_t N, int nc, const S* __res
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   auto to_row = [&](int64_t e, S v) {
-    if (e < ncam) p_cam[(e / 9) * CamPad<S>::n + e % 9] = v;
+    if (e < ncam) p_cam[(e / 9) * row_stride + row_off + e % 9] = v;
   };
   const int64_t n4 = N / 4;
   const V* __restrict__ z4 = reinterpret_cast<const V*>(z);
@@ -515,7 +516,7 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
       CBA_LAUNCHED();
       k_pcg_scalar1<<<1, 1024, 0, st>>>((int)ug, h->partials, h->scal);
       CBA_LAUNCHED();
-      k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, (S*)h->p_cam, h->scal);
+      k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, (S*)h->p_cam, cam_row_stride<S>(h), cam_row_p_off(h), h->scal);
       CBA_LAUNCHED();
     }
     launched += check_every;
