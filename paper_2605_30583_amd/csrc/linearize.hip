@@ -241,6 +241,45 @@ __global__ void k_lin_orphans(int n_orphan, S* g, S* D, double* Hpp, int nc) {
 // ---------------------------------------------------------------------------
 // Camera-major block sums: one workgroup per chunk.
 // ---------------------------------------------------------------------------
+
+// One butterfly step of a wave reduce-scatter over N (even) values: lanes
+// with bit M clear keep the sums of values [0, N/2), lanes with it set those
+// of [N/2, N), both in positions [0, N/2).
+template <int N, int M>
+__device__ inline void scatter_step(double* v, int lane) {
+  constexpr int H = N / 2;
+  const bool up = (lane & M) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = up ? v[i] : v[i + H];
+    const double keep = up ? v[i + H] : v[i];
+    v[i] = keep + __shfl_xor(send, M, kWave);
+  }
+}
+
+// Wave sums of the kCamRowWidth (54) values in v, one per lane: returns the
+// index of the sum this lane holds in v[0], or -1.  Six butterfly steps move
+// 27 + 14 + 7 + 4 + 2 + 1 values per lane instead of six per value; the
+// halves of odd length are padded with a zero.
+__device__ inline int wave_scatter54(double* v, int lane) {
+  static_assert(kCamRowWidth == 54, "reduce-scatter is laid out for 54 values");
+  scatter_step<54, 32>(v, lane);
+  v[27] = 0.0;
+  scatter_step<28, 16>(v, lane);
+  scatter_step<14, 8>(v, lane);
+  v[7] = 0.0;
+  scatter_step<8, 4>(v, lane);
+  scatter_step<4, 2>(v, lane);
+  scatter_step<2, 1>(v, lane);
+  const int pos3 = (lane & 4) + (lane & 2) + (lane & 1);           // of 7 (+ pad)
+  const int pos1 = ((lane & 16) ? 14 : 0) + ((lane & 8) ? 7 : 0) + pos3;  // of 27 (+ pad)
+  if (pos3 >= 7 || pos1 >= 27) return -1;
+  return ((lane & 32) ? 27 : 0) + pos1;
+}
+
+// Each thread takes the chunk's observations tid, tid + 256, ... (at most
+// kCamChunk / 256 of them): their point indices, points and pixels are all
+// requested before the first block is evaluated.
 template <typename S>
 __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chunks,
                                                   const int* __restrict__ cm_pt,
@@ -248,18 +287,29 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
                                                   const double* __restrict__ cam,
                                                   const S* __restrict__ pts,
                                                   double* __restrict__ rows, int loss, double loss_c) {
+  constexpr int kPer = kCamChunk / 256;
   __shared__ double lds[4][kCamRowWidth];
   const Chunk ch = chunks[blockIdx.x];
+  const int tid = threadIdx.x;
+  int jj[kPer];
+  S xp[kPer][3];
+  double2 q[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) jj[i] = cm_pt[min(ch.begin + tid + 256 * i, ch.end - 1)];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    load_point<S>(pts, (size_t)jj[i], xp[i]);
+    q[i] = reinterpret_cast<const double2*>(cm_px)[min(ch.begin + tid + 256 * i, ch.end - 1)];
+  }
   const Cam<S> c = load_cam<S>(cam, ch.cam);
   double acc[kCamRowWidth];
 #pragma unroll
   for (int k = 0; k < kCamRowWidth; ++k) acc[k] = 0.0;
-  for (int j = ch.begin + threadIdx.x; j < ch.end; j += blockDim.x) {
-    S xp[3];
-    load_point<S>(pts, (size_t)cm_pt[j], xp);
-    const double2 q = reinterpret_cast<const double2*>(cm_px)[j];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if (ch.begin + tid + 256 * i >= ch.end) break;
     S r0, r1, col[12][2];
-    snavely_jacobian<S>(c, xp[0], xp[1], xp[2], (S)q.x, (S)q.y, r0, r1, col);
+    snavely_jacobian<S>(c, xp[i][0], xp[i][1], xp[i][2], (S)q[i].x, (S)q[i].y, r0, r1, col);
     if (loss != CASPAR_LOSS_TRIVIAL) {
       // the same weight as the point side computes for this observation
       double w;
@@ -286,16 +336,13 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
       for (int l = k; l < 9; ++l)
         acc[9 + tri9(k, l)] = fma(jc[k][0], jc[l][0], fma(jc[k][1], jc[l][1], acc[9 + tri9(k, l)]));
   }
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < kCamRowWidth; ++k) {
-    const double s = wave_sum(acc[k]);
-    if (lane == 0) lds[wv][k] = s;
-  }
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int idx = wave_scatter54(acc, lane);
+  if (idx >= 0) lds[wv][idx] = acc[0];
   __syncthreads();
-  if (threadIdx.x < kCamRowWidth) {
-    const double s = lds[0][threadIdx.x] + lds[1][threadIdx.x] + lds[2][threadIdx.x] + lds[3][threadIdx.x];
-    rows[(size_t)blockIdx.x * kCamRowWidth + threadIdx.x] = s;
+  if (tid < kCamRowWidth) {
+    const double s = lds[0][tid] + lds[1][tid] + lds[2][tid] + lds[3][tid];
+    rows[(size_t)blockIdx.x * kCamRowWidth + tid] = s;
   }
 }
 
