@@ -39,12 +39,15 @@ HBM_PEAK_GBS = 8000.0
 # Float32 / float64 vector FMA issue without packed math (this build does not
 # use packed float32): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Algorithmic flops of the fused product per observation: evaluating the
-# 2x9 / 2x3 blocks from the camera and the point (P = R X + t, projection,
-# distortion, the 2x3 chain factor, J_p = B R, J_w = -J_p [X]x, the three
-# calibration columns: 113) when they are not stored, plus applying them
-# (q = J p, J_c^T q, J_p^T q, |q|^2 and the sums: 100).
-FLOPS_PER_OBS = {"recompute": 213.0, "stored": 100.0}
+# Algorithmic flops of the fused product per observation (FMA = 2).
+# Stored blocks: q = J p (48), J_c^T q and J_p^T q (36), |q|^2 and the
+# camera and point sums (16): 100.  Recomputed blocks, applied in factored
+# form without forming them: R from the camera's unit quaternion (24); P,
+# the projection, distortion and the 2x3 chain factor B (51); q = B (R (p_X +
+# p_w x X) + p_t) + calibration term (50); B^T q, R^T B^T q, X x R^T B^T q,
+# the calibration transposes and q.q (43); the sums as with stored blocks
+# (16): 184.
+FLOPS_PER_OBS = {"recompute": 184.0, "stored": 100.0}
 PROFILES = os.path.join(ROOT, "profiles")
 
 

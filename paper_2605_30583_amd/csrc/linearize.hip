@@ -346,28 +346,38 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
   }
 }
 
-// Per camera (one workgroup): sum the chunk rows into g_c, H_cc and D_c;
-// each wave takes every fourth of the 54 values, lanes stride the chunks.
+// Per camera (one workgroup): sum the chunk rows into g_c, H_cc and D_c.
+// Lane k of each wave takes value k (k < 54) of every fourth chunk, so each
+// wave reads whole 432-byte rows; the four wave sums are added in LDS.
 template <typename S>
 __global__ __launch_bounds__(256) void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
                                                        const double* __restrict__ rows, S* g, S* D,
                                                        double* Hcc) {
+  __shared__ double red[4][kCamRowWidth];
   const int c = blockIdx.x;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int k = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int q0 = chunk_off[c], q1 = chunk_off[c + 1];
-  for (int k = wv; k < kCamRowWidth; k += 4) {
-    double s = 0.0;
-    for (int q = q0 + lane; q < q1; q += kWave) s += rows[(size_t)q * kCamRowWidth + k];
-    s = wave_sum(s);
-    if (lane == 0) {
-      if (k < 9) {
-        g[9 * (size_t)c + k] = (S)s;
-      } else {
-        const int hidx = k - 9;
-        Hcc[45 * (size_t)c + hidx] = s;
-        for (int d = 0; d < 9; ++d)
-          if (tri9(d, d) == hidx) D[9 * (size_t)c + d] = (S)clamp_diag(s);
-      }
+  if (k < kCamRowWidth) {
+    double s0 = 0.0, s1 = 0.0;
+    int q = q0 + wv;
+    for (; q + 4 < q1; q += 8) {
+      s0 += rows[(size_t)q * kCamRowWidth + k];
+      s1 += rows[(size_t)(q + 4) * kCamRowWidth + k];
+    }
+    if (q < q1) s0 += rows[(size_t)q * kCamRowWidth + k];
+    red[wv][k] = s0 + s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < kCamRowWidth) {
+    const int t = threadIdx.x;
+    const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    if (t < 9) {
+      g[9 * (size_t)c + t] = (S)s;
+    } else {
+      const int hidx = t - 9;
+      Hcc[45 * (size_t)c + hidx] = s;
+      for (int d = 0; d < 9; ++d)
+        if (tri9(d, d) == hidx) D[9 * (size_t)c + d] = (S)clamp_diag(s);
     }
   }
 }
