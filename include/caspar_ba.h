@@ -80,7 +80,8 @@ enum {
   CASPAR_EINVAL = -1,   /* bad argument, index out of range, non-finite input */
   CASPAR_EHIP = -2,     /* a HIP runtime call failed */
   CASPAR_ENOMEM = -3,   /* workspace smaller than caspar_ba_workspace_bytes() */
-  CASPAR_ENUMERIC = -4  /* non-finite cost or PCG breakdown at the first step */
+  CASPAR_ENUMERIC = -4, /* non-finite cost or PCG breakdown at the first step */
+  CASPAR_EIO = -5       /* a file could not be opened, read or written */
 };
 
 /* Solver options; caspar_default_solve_opts() fills the defaults. */
@@ -259,6 +260,38 @@ CASPAR_API int caspar_ba_set_timing(caspar_ba* h, int enable);
 CASPAR_API int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out);
 
 CASPAR_API void caspar_ba_destroy(caspar_ba* h);
+
+/* BAL problem files.  The paper evaluates on the Bundle Adjustment in the
+ * Large datasets (Section VI); these calls read and write their text format,
+ * a stream of whitespace-separated tokens:
+ *   n_cams n_points n_obs
+ *   n_obs records    camera_index point_index x y
+ *   n_cams records   9 values: angle-axis rotation (3), translation (3), f, k1, k2
+ *   n_points records 3 values
+ * which is the boundary's own layout, so the arrays go to create() as they
+ * are.  All pointers are (host) and owned by the caller; no GPU is touched.
+ *
+ * read_header: the three counts of the file at path (outs may be NULL).
+ * read: the whole problem into caller arrays sized from the header:
+ *   obs_cam[n_obs], obs_pt[n_obs] (int32), px[n_obs][2], cams[n_cams][9],
+ *   points[n_points][3] (float64).  The sizes passed must equal the header's.
+ *   Reals are parsed correctly rounded, so a file written with round-trip
+ *   precision reads back bit for bit.  The file is tokenised by up to 16 host
+ *   threads.
+ * write: the same arrays to path (created or truncated), every real in its
+ *   shortest round-trip form.
+ * Errors: CASPAR_EIO when the file cannot be opened, read or written;
+ * CASPAR_EINVAL for a malformed header, a token that is not a number, a
+ * non-finite value, an index out of range, too few or too many values, sizes
+ * that differ from the header, or a NULL array; the message names the
+ * offending record.  A failed read may leave the output arrays partly
+ * written. */
+CASPAR_API int caspar_bal_read_header(const char* path, int32_t* n_cams, int32_t* n_points, int64_t* n_obs);
+CASPAR_API int caspar_bal_read(const char* path, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                               int32_t* obs_cam, int32_t* obs_pt, double* px, double* cams, double* points);
+CASPAR_API int caspar_bal_write(const char* path, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                                const int32_t* obs_cam, const int32_t* obs_pt, const double* px,
+                                const double* cams, const double* points);
 
 /* Message of the last failed call on this thread ("" if none). */
 CASPAR_API const char* caspar_last_error(void);

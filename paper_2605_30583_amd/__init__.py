@@ -6,5 +6,5 @@ The Python layer only marshals torch tensors (device memory, streams) into
 the C calls; every step of the solve runs in the HIP library.  Importing the
 package is cheap; the library is loaded on first use and its absence raises.
 """
-from .api import (BundleAdjuster, SolveOptions, BAFunction, project,  # noqa: F401
+from .api import (BundleAdjuster, SolveOptions, BAFunction, project, read_bal, write_bal,  # noqa: F401
                   FP64, FP32_MIXED, RECOMPUTE_JACOBIAN, library_path)

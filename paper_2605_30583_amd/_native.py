@@ -11,7 +11,8 @@ FP32_MIXED = 1
 ADJ_GAUGE_PROJECT = 1
 RECOMPUTE_JACOBIAN = 0x10
 LOSS_TRIVIAL, LOSS_HUBER, LOSS_CAUCHY = 0, 1, 2
-STATUS = {0: "CASPAR_OK", -1: "CASPAR_EINVAL", -2: "CASPAR_EHIP", -3: "CASPAR_ENOMEM", -4: "CASPAR_ENUMERIC"}
+STATUS = {0: "CASPAR_OK", -1: "CASPAR_EINVAL", -2: "CASPAR_EHIP", -3: "CASPAR_ENOMEM", -4: "CASPAR_ENUMERIC",
+          -5: "CASPAR_EIO"}
 
 
 class SolveOpts(C.Structure):
@@ -58,6 +59,10 @@ SIGNATURES = [
     ("caspar_ba_pcg", C.c_int, [_P, C.c_double, _P, C.c_double, C.c_int32, _P, C.POINTER(C.c_int32), _D]),
     ("caspar_ba_cost_fp64", C.c_int, [_P, _D]),
     ("caspar_project", C.c_int, [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
+    ("caspar_bal_read_header", C.c_int, [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int64)]),
+    ("caspar_bal_read", C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P]),
+    ("caspar_bal_write", C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P]),
     ("caspar_ba_layout_info", C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_int32)]),
     ("caspar_ba_set_timing", C.c_int, [_P, C.c_int]),

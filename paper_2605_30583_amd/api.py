@@ -222,6 +222,52 @@ class BundleAdjuster:
         return {"hot_cams": k.value, "cold_obs": cold.value, "n_tiles": tiles.value, "matvec_groups": groups.value}
 
 
+def read_bal(path) -> dict:
+    """A BAL problem file as host numpy arrays in the boundary's layout:
+    cams [n_cams, 9] (angle-axis, t, f, k1, k2), points [n_points, 3],
+    obs_cam / obs_pt [n_obs] (int32), px [n_obs, 2] (float64)."""
+    import numpy as np
+    lib = _native.load()
+    bp = _path_bytes(path)
+    nc, npnt, no = C.c_int32(), C.c_int32(), C.c_int64()
+    check(lib.caspar_bal_read_header(bp, C.byref(nc), C.byref(npnt), C.byref(no)))
+    out = {"cams": np.empty((nc.value, 9), np.float64), "points": np.empty((npnt.value, 3), np.float64),
+           "obs_cam": np.empty(no.value, np.int32), "obs_pt": np.empty(no.value, np.int32),
+           "px": np.empty((no.value, 2), np.float64)}
+    check(lib.caspar_bal_read(bp, nc.value, npnt.value, no.value, *(_host_ptr(out[k]) for k in
+                                                                      ("obs_cam", "obs_pt", "px", "cams", "points"))))
+    return out
+
+
+def write_bal(path, cams, points, obs_cam, obs_pt, px) -> None:
+    """Write a problem (host arrays or tensors, boundary layout) as a BAL file."""
+    import numpy as np
+    lib = _native.load()
+    a = {"cams": (cams, np.float64, 9), "points": (points, np.float64, 3), "obs_cam": (obs_cam, np.int32, None),
+         "obs_pt": (obs_pt, np.int32, None), "px": (px, np.float64, 2)}
+    h = {}
+    for k, (v, dt, width) in a.items():
+        v = v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else v
+        v = np.ascontiguousarray(v, dtype=dt)
+        if width is not None and (v.ndim != 2 or v.shape[1] != width):
+            raise ValueError(f"{k} must have shape [n, {width}]")
+        h[k] = v
+    no = h["obs_cam"].shape[0]
+    if h["obs_pt"].shape != (no,) or h["px"].shape[0] != no:
+        raise ValueError("obs_cam, obs_pt and px must describe the same observations")
+    check(lib.caspar_bal_write(_path_bytes(path), h["cams"].shape[0], h["points"].shape[0], no,
+                               *(_host_ptr(h[k]) for k in ("obs_cam", "obs_pt", "px", "cams", "points"))))
+
+
+def _path_bytes(path) -> bytes:
+    import os
+    return os.fsencode(path)
+
+
+def _host_ptr(a):
+    return C.c_void_p(a.ctypes.data if a.size else 0)
+
+
 class BAFunction(torch.autograd.Function):
     """(obs_px, cams0, points0) -> optimal (cams*, points*) with the implicit
     adjoint as backward: d L / d obs_px = J v, (J^T J + lambda_adj D) v = g.
