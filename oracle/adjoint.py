@@ -17,18 +17,23 @@ from __future__ import annotations
 
 import numpy as np
 
+import scipy.sparse as sp
+
+from . import between as between_mod
 from . import camera, linear, robust
 
 
 def implicit_grad_obs(state: camera.State, obs_cam, obs_pt, obs_px, g_theta: np.ndarray,
                       lam: float, method: str = "schur", loss: str = "trivial",
-                      loss_scale: float = 1.0) -> np.ndarray:
+                      loss_scale: float = 1.0, between=None) -> np.ndarray:
     """dL/dpx [n_obs, 2] for the tangent gradient g_theta at state.
 
     With a robust loss the IRLS weights are held fixed (the Gauss-Newton
     reading of the optimality condition sum_o w_o J_o^T r_o = 0): the system
     uses the sqrt(w)-scaled blocks J~ and dL/dpx_o = w_o J_o v =
-    sqrt(w_o) J~_o v."""
+    sqrt(w_o) J~_o v.  Pose between-factors (fi, fj, Z, w) join the system
+    matrix; they hold no pixels, so dL/dpx keeps one row pair per
+    observation."""
     if loss == "trivial":
         _, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
         sw = np.ones(np.asarray(obs_cam).shape[0])
@@ -36,11 +41,16 @@ def implicit_grad_obs(state: camera.State, obs_cam, obs_pt, obs_px, g_theta: np.
         _, _, Jc, Jp, w = robust.linearize(state, obs_cam, obs_pt, obs_px, loss, loss_scale)
         sw = np.sqrt(w)
     J = linear.jacobian_csr(Jc, Jp, obs_cam, obs_pt, state.n_cams, state.n_points)
-    D = linear.damping_diagonal(J)
+    Jsys = J
+    if between is not None:
+        _, Ji, Jj = between_mod.linearize(state, *between)
+        Jsys = sp.vstack([J, between_mod.jacobian_csr(Ji, Jj, between[0], between[1], state.n_cams,
+                                                      state.n_points)]).tocsr()
+    D = linear.damping_diagonal(Jsys)
     if method == "dense":
-        v = linear.solve_dense(J, D, lam, g_theta)
+        v = linear.solve_dense(Jsys, D, lam, g_theta)
     else:
-        v = linear.solve_schur(J, D, lam, g_theta, state.n_cams, state.n_points)
+        v = linear.solve_schur(Jsys, D, lam, g_theta, state.n_cams, state.n_points)
     return (J @ v).reshape(-1, 2) * sw[:, None]
 
 

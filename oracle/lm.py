@@ -24,6 +24,10 @@ With a robust loss (robust.py) the cost is 1/2 sum rho(|r|^2) and each
 linearisation uses the IRLS-scaled residuals and blocks; the gain ratio
 compares the robust cost decrease with that weighted model's prediction.
 
+With pose between-factors (between.py; the robust loss applies to the
+reprojection factors only) their six residual rows join the system: the
+cost adds 1/2 sum |r_b|^2 and J, g and D are those of the stacked rows.
+
 Pins (tests/test_oracle_lm.py): zero-noise problems converge to F ~ 0,
 accepted costs decrease monotonically, the noisy optimum matches the
 chi-square expectation, an independent solver (scipy least_squares on an
@@ -35,7 +39,9 @@ from __future__ import annotations
 import dataclasses
 
 import numpy as np
+import scipy.sparse as sp
 
+from . import between as between_mod
 from . import camera, linear, pcg as pcg_mod, robust
 
 
@@ -54,6 +60,7 @@ class LMOptions:
     pred_tol: float = 0.0           # stop when pred <= pred_tol * F (0: never)
     loss: str = "trivial"           # "trivial" | "huber" | "cauchy" (robust.py)
     loss_scale: float = 1.0
+    between: tuple | None = None    # (fi, fj, Z [n, 6], w [n, 2]) pose between-factors (between.py)
 
 
 @dataclasses.dataclass
@@ -77,16 +84,31 @@ class LMResult:
     stop_reason: str
 
 
-def _linearize(state, obs_cam, obs_pt, obs_px, loss="trivial", scale=1.0):
+def _linearize(state, obs_cam, obs_pt, obs_px, loss="trivial", scale=1.0, between=None):
     if loss == "trivial":
         r, Jc, Jp = camera.linearize(state, obs_cam, obs_pt, obs_px)
         F = 0.5 * float(np.sum(r * r))
     else:
         F, r, Jc, Jp, _ = robust.linearize(state, obs_cam, obs_pt, obs_px, loss, scale)
     J = linear.jacobian_csr(Jc, Jp, obs_cam, obs_pt, state.n_cams, state.n_points)
+    r = np.asarray(r).ravel()
+    if between is not None:
+        rb, Ji, Jj = between_mod.linearize(state, *between)
+        F += 0.5 * float(np.sum(rb * rb))
+        J = sp.vstack([J, between_mod.jacobian_csr(Ji, Jj, between[0], between[1], state.n_cams,
+                                                   state.n_points)]).tocsr()
+        r = np.concatenate([r, rb.ravel()])
     g = linear.gradient(J, r)
     D = linear.damping_diagonal(J)
     return F, J, g, D
+
+
+def total_cost(state, obs_cam, obs_pt, obs_px, opts: "LMOptions") -> float:
+    """The objective: reprojection cost (robust if set) plus the between-factor cost."""
+    F = robust.cost(state, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
+    if opts.between is not None:
+        F += between_mod.cost(state, *opts.between)
+    return F
 
 
 def solve_step(J, D, lam, b, n_cams, n_points, opts: LMOptions):
@@ -107,7 +129,7 @@ def solve_step(J, D, lam, b, n_cams, n_points, opts: LMOptions):
 def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None = None) -> LMResult:
     opts = opts or LMOptions()
     state = state.copy()
-    lin = lambda st: _linearize(st, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
+    lin = lambda st: _linearize(st, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale, opts.between)
     F, J, g, D = lin(state)
     F0 = F
     g0 = float(np.max(np.abs(g))) if g.size else 0.0
@@ -128,7 +150,7 @@ def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None =
             reason = "pred"
             break
         trial = state.retract(delta)
-        Ft = robust.cost(trial, obs_cam, obs_pt, obs_px, opts.loss, opts.loss_scale)
+        Ft = total_cost(trial, obs_cam, obs_pt, obs_px, opts)
         rho = (F - Ft) / pred if (pred > 0.0 and np.isfinite(Ft)) else -np.inf
         lam_used = lam
         if rho > 0.0:

@@ -211,3 +211,30 @@ def scene_config(name: str, **overrides) -> Scene:
     cfg = dict(SCENE_CONFIGS[name])
     cfg.update(overrides)
     return make_scene(**cfg)
+
+
+@dataclasses.dataclass
+class BetweenDraws:
+    """Camera pairs for pose between-factors and their standard-normal noise
+    draws; forming the measurements from the true poses is left to the
+    caller (it is the factor's own arithmetic)."""
+    fi: np.ndarray           # [n] int32 first camera of each pair
+    fj: np.ndarray           # [n] int32 second camera
+    rot_noise: np.ndarray    # [n, 3] N(0, 1)
+    trans_noise: np.ndarray  # [n, 3] N(0, 1)
+
+
+def between_draws(n_cams: int, seed: int, n_loops: int = 0) -> BetweenDraws:
+    """A chain (c, c + 1) over the cameras in caller order, then n_loops
+    random pairs of distinct cameras (loop closures), then the noise draws,
+    in that order from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    fi = list(range(n_cams - 1))
+    fj = list(range(1, n_cams))
+    for _ in range(n_loops):
+        a, b = rng.choice(n_cams, size=2, replace=False)
+        fi.append(int(a))
+        fj.append(int(b))
+    n = len(fi)
+    return BetweenDraws(np.asarray(fi, np.int32), np.asarray(fj, np.int32), rng.normal(size=(n, 3)),
+                        rng.normal(size=(n, 3)))

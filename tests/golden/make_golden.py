@@ -1,6 +1,7 @@
 """Writes tests/golden/lm_reference.json: the oracle's Levenberg-Marquardt
-results on the synthetic workloads (plain least squares, and the robust
-losses on the tiny scene with planted outliers).
+results on the synthetic workloads (plain least squares, the robust losses
+on the tiny scene with planted outliers, and the tiny scene with pose
+between-factors: a camera chain plus four loop closures).
 
 Calls only synth/ and oracle/ (exact Schur-complement steps, float64).
 Run from the repository root:
@@ -17,17 +18,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import camera, lm  # noqa: E402
-from synth import scene_config  # noqa: E402
+from oracle import between, camera, lm  # noqa: E402
+from synth import between_draws, scene_config  # noqa: E402
 
-# run name -> (scene, LM iterations, loss, loss scale in pixels)
+# run name -> (scene, LM iterations, loss, loss scale in pixels, between-factors)
+# between-factors: (draw seed, loop closures, rotation sigma, translation sigma)
+BETWEEN = (21, 4, 2e-3, 1e-2)
 RUNS = {
-    "tiny": ("tiny", 20, "trivial", 1.0),
-    "medium": ("medium", 30, "trivial", 1.0),
-    "bal1700": ("bal1700", 20, "trivial", 1.0),
-    "tiny_outliers_huber": ("tiny_outliers", 40, "huber", 3.0),
-    "tiny_outliers_cauchy": ("tiny_outliers", 40, "cauchy", 3.0),
+    "tiny": ("tiny", 20, "trivial", 1.0, None),
+    "medium": ("medium", 30, "trivial", 1.0, None),
+    "bal1700": ("bal1700", 20, "trivial", 1.0, None),
+    "tiny_outliers_huber": ("tiny_outliers", 40, "huber", 3.0, None),
+    "tiny_outliers_cauchy": ("tiny_outliers", 40, "cauchy", 3.0, None),
+    "tiny_between": ("tiny", 20, "trivial", 1.0, BETWEEN),
 }
+
+
+def between_for(sc, spec):
+    seed, loops, rs, ts = spec
+    d = between_draws(sc.n_cams, seed, loops)
+    st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
+    Z, w = between.measurements(st_true, d.fi, d.fj, d.rot_noise, d.trans_noise, rs, ts)
+    return d.fi, d.fj, Z, w
 
 
 def main():
@@ -39,19 +51,21 @@ def main():
         out["runs"] = json.load(open(path))["runs"]
     names = sys.argv[1:] or list(RUNS)
     for name in names:
-        scene, iters, loss, scale = RUNS[name]
+        scene, iters, loss, scale, bspec = RUNS[name]
         sc = scene_config(scene)
         st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
         px = camera.project(st_true, sc.obs_cam, sc.obs_pt) + sc.noise
         st = camera.State.from_bal(sc.cams_init, sc.points_init)
         t = time.time()
+        bf = between_for(sc, bspec) if bspec else None
         res = lm.solve(st, sc.obs_cam, sc.obs_pt, px,
-                       lm.LMOptions(max_iters=iters, inner="schur", loss=loss, loss_scale=scale))
+                       lm.LMOptions(max_iters=iters, inner="schur", loss=loss, loss_scale=scale, between=bf))
         out["runs"][name] = {
             "scene": scene,
             "loss": loss,
             "loss_scale": scale,
             "max_iters": iters,
+            "between": list(bspec) if bspec else None,
             "initial_cost": res.initial_cost,
             "final_cost": res.final_cost,
             "stop_reason": res.stop_reason,
