@@ -261,6 +261,38 @@ CASPAR_API int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out);
 
 CASPAR_API void caspar_ba_destroy(caspar_ba* h);
 
+/* Pose between-factors: a second factor type on pairs of cameras (the
+ * paper's solvers take any collection of factor types, an odometry factor
+ * being its example, Section V).  Factor f between cameras a = cam_i[f] and
+ * b = cam_j[f] (caller indices, a != b) with measured relative pose
+ * Z = meas[f] = (angle-axis (3), translation (3)) of T_b T_a^-1 (world-to-
+ * camera poses T = (R, t)) and square-root weights weights[f] = (s_rot,
+ * s_trans) > 0 has the residual
+ *   r = [ s_rot   Log(Z_R^T R_b R_a^T) ;  s_trans (t_b - R_b R_a^T t_a - Z_t) ]
+ * and adds 1/2 |r|^2 to the cost.  The factors enter the linearisation
+ * (gradient, camera blocks, damping diagonal), every product, the trial
+ * cost, caspar_ba_cost_fp64, solve and backward; robust losses apply to the
+ * reprojection factors only.  The parity hook caspar_ba_linearize still
+ * exports the reprojection residuals and blocks alone (its g and D include
+ * the factors).  backward() refuses CASPAR_ADJ_GAUGE_PROJECT while factors
+ * are set: they fix the scale, so the similarity gauge is no longer free.
+ *
+ * between_workspace_bytes: device bytes set_between needs for n_factors on a
+ *   problem of n_cams cameras.
+ * set_between: copies the factors (host arrays: cam_i, cam_j [n], meas
+ *   [n][6], weights [n][2]) into dev_workspace (dev, 256-byte aligned, at
+ *   least between_workspace_bytes; the caller owns it and keeps it alive
+ *   until the handle is destroyed or set_between is called again).  Replaces
+ *   any earlier set; n_factors = 0 removes them (the workspace may then be
+ *   NULL).  The next solve/linearize re-linearises.  CASPAR_EINVAL for an
+ *   index out of range, equal cameras, a non-finite measurement, a weight
+ *   that is not finite and positive, or a workspace that is too small or
+ *   misaligned. */
+CASPAR_API size_t caspar_ba_between_workspace_bytes(int32_t n_factors, int32_t n_cams);
+CASPAR_API int caspar_ba_set_between(caspar_ba* h, int32_t n_factors, const int32_t* cam_i,
+                                     const int32_t* cam_j, const double* meas, const double* weights,
+                                     void* dev_workspace, size_t workspace_bytes);
+
 /* BAL problem files.  The paper evaluates on the Bundle Adjustment in the
  * Large datasets (Section VI); these calls read and write their text format,
  * a stream of whitespace-separated tokens:

@@ -59,6 +59,8 @@ SIGNATURES = [
     ("caspar_ba_pcg", C.c_int, [_P, C.c_double, _P, C.c_double, C.c_int32, _P, C.POINTER(C.c_int32), _D]),
     ("caspar_ba_cost_fp64", C.c_int, [_P, _D]),
     ("caspar_project", C.c_int, [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
+    ("caspar_ba_between_workspace_bytes", C.c_size_t, [C.c_int32, C.c_int32]),
+    ("caspar_ba_set_between", C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, C.c_size_t]),
     ("caspar_bal_read_header", C.c_int, [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int64)]),
     ("caspar_bal_read", C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P]),

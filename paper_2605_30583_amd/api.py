@@ -117,6 +117,34 @@ class BundleAdjuster:
     def _vec(self):
         return torch.empty(self.n_params, dtype=torch.float64, device=self.device)
 
+    def set_between(self, cam_i, cam_j, meas, weights):
+        """Pose between-factors (caspar_ba_set_between): camera pairs [n] (int32),
+        measured relative poses [n, 6] (angle-axis, translation of T_j T_i^-1)
+        and square-root weights [n, 2] (rotation, translation), host arrays or
+        tensors.  An empty set removes them.  The device workspace they need
+        is allocated here and kept with the adjuster."""
+        import numpy as np
+
+        def host(v, dt):
+            v = v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else v
+            return np.ascontiguousarray(v, dtype=dt)
+
+        ci, cj = host(cam_i, np.int32).ravel(), host(cam_j, np.int32).ravel()
+        n = ci.shape[0]
+        z, w = host(meas, np.float64).reshape(n, 6), host(weights, np.float64).reshape(n, 2)
+        if cj.shape[0] != n:
+            raise ValueError("cam_i and cam_j must have the same length")
+        if n == 0:
+            check(self._lib.caspar_ba_set_between(self._h, 0, None, None, None, None, None, 0))
+            self._between_ws = None
+            return
+        nbytes = self._lib.caspar_ba_between_workspace_bytes(n, self.n_cams)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+        check(self._lib.caspar_ba_set_between(self._h, n, _host(ci), _host(cj), _host(z), _host(w), C.c_void_p(ptr),
+                                              nbytes))
+        self._between_ws = ws
+
     def solve(self, opts: SolveOptions | None = None, history: bool = False):
         opts = opts or SolveOptions()
         st = _native.SolveStats()
@@ -266,6 +294,9 @@ def _path_bytes(path) -> bytes:
 
 def _host_ptr(a):
     return C.c_void_p(a.ctypes.data if a.size else 0)
+
+
+_host = _host_ptr
 
 
 class BAFunction(torch.autograd.Function):

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcaspar_ba.so")
-SOURCES = ["layout.hip", "linearize.hip", "matvec.hip", "pcg.hip", "solver.hip", "bal_io.hip"]
+SOURCES = ["layout.hip", "linearize.hip", "matvec.hip", "pcg.hip", "solver.hip", "between.hip", "bal_io.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden",

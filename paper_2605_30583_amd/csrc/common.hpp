@@ -116,6 +116,17 @@ struct Chunk {
 };
 
 // Points observed more than kTileMax times: their tiles' partial rows.
+// A pose between-factor in internal camera ids: measured relative pose
+// (Z_R row-major, Z_t) and the square-root weights of its rotation and
+// translation rows.  128 bytes.
+struct BetweenFactor {
+  int ci, cj;
+  double ZR[9];
+  double Zt[3];
+  double s_rot, s_trans;
+  double pad;
+};
+
 struct SplitPoint {
   int pt, row_begin, nrows, pad;
 };
@@ -124,6 +135,8 @@ struct SplitPoint {
 struct DevScalars {
   double pAp, alpha, rho, rr, bb, tol2, beta, pad0;
   int iter, done, reason, max_iter;
+  // reduction results: [0] linearisation cost sum, [1] trial cost sum, [2] dot,
+  // [3] absmax, [4..6] predicted-decrease dots, [7] between-factor r.r
   double red[8];
   int err;
   int pad1[3];
@@ -225,6 +238,13 @@ struct caspar_ba {
   void* Mp = nullptr;           // [np][6]
   cba::Vectors vec;
 
+  // pose between-factors (in the caller's second workspace, set_between)
+  int n_between = 0;
+  cba::BetweenFactor* between = nullptr;  // [n_between]
+  int* bt_off = nullptr;        // [nc + 1] incident factors of each internal camera
+  int* bt_inc = nullptr;        // [2 n_between] factor * 2 + side (0: first camera, 1: second)
+  double* bt_rows = nullptr;    // [nc][6] between part of the product's camera rows
+
   double* partials = nullptr;   // [kMaxPartials][4]
   double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
   cba::DevScalars* scal = nullptr;
@@ -320,6 +340,11 @@ void timing_mark_start(caspar_ba* h);
 void timing_mark_stop(caspar_ba* h);
 void timing_harvest(caspar_ba* h, int effective);  // after a sync: count the first `effective` launches
 double matvec_algorithmic_bytes(const caspar_ba* h);
+// between.hip
+void run_between_lin(caspar_ba* h);                 // adds g, H_cc, D terms; cost sum r.r into red[7]
+double run_between_cost(caspar_ba* h, const double* cam);  // 1/2 sum |r|^2 at camera rows `cam`
+void run_between_product(caspar_ba* h, const void* p, bool pcg_mode);  // bt_rows and pAp partials
+unsigned between_grid(const caspar_ba* h);          // workgroups of the per-camera between kernels
 int matvec_waves(int prec, bool rj);  // waves per workgroup of the fused product
 // helpers
 void sync(caspar_ba* h);
@@ -342,6 +367,11 @@ template <>
 struct Scalar<float> {
   static constexpr float eps() { return 10.0f * 1.1920928955078125e-07f; }
 };
+
+// Index of (k, l), k <= l, in the row-major upper triangle of a 9x9 block.
+__host__ __device__ constexpr int tri9(int k, int l) { return k * 9 - k * (k - 1) / 2 + (l - k); }
+
+__device__ inline double clamp_diag(double d) { return fmin(fmax(d, 1e-6), 1e32); }
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll

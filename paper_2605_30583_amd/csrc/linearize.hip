@@ -16,10 +16,6 @@
 
 namespace cba {
 
-__host__ __device__ constexpr int tri9(int k, int l) { return k * 9 - k * (k - 1) / 2 + (l - k); }
-
-__device__ inline double clamp_diag(double d) { return fmin(fmax(d, 1e-6), 1e32); }
-
 // Camera table in the working precision (used when the Jacobian is
 // recomputed; the conversion matches the one the linearisation applies).
 template <typename S>
@@ -599,6 +595,7 @@ static void linearize_t(caspar_ba* h) {
     k_lin_cam_final<S><<<h->nc, 256, 0, st>>>(h->nc, h->chunk_off, h->chunk_rows, g, D, h->Hcc);
     CBA_LAUNCHED();
   }
+  run_between_lin(h);  // pose between-factors: their g, H_cc, D terms and cost
 }
 
 void run_linearize(caspar_ba* h) {
@@ -607,14 +604,15 @@ void run_linearize(caspar_ba* h) {
   else
     linearize_t<float>(h);
   const DevScalars s = read_scalars(h);
-  h->cost = 0.5 * s.red[0];
+  h->cost = 0.5 * (s.red[0] + (h->n_between > 0 ? s.red[7] : 0.0));
   h->gmax = run_absmax(h, h->vec.g);
   h->linearized = true;
   h->bj_lambda = -1.0;
 }
 
 double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
-  if (h->n_tiles == 0) return 0.0;
+  const double fb = run_between_cost(h, cam);  // pose between-factors (float64)
+  if (h->n_tiles == 0) return fb;
   hipStream_t st = h->stream;
   const bool f64 = fp64 || h->prec == CASPAR_FP64;
   const unsigned tg = f64 ? tile_grid<k_cost<double>>(h->n_tiles) : tile_grid<k_cost<float>>(h->n_tiles);
@@ -633,7 +631,7 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
   CBA_LAUNCHED();
   k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 1);
   CBA_LAUNCHED();
-  return 0.5 * read_scalars(h).red[1];
+  return 0.5 * read_scalars(h).red[1] + fb;
 }
 
 template <typename S>

@@ -427,7 +427,12 @@ __global__ __launch_bounds__(256) void k_matvec_final(
     const int* __restrict__ cold_list, const S* __restrict__ p, const S* __restrict__ D, double lambda,
     S* __restrict__ w, int n_split, const SplitPoint* __restrict__ sp, const double* __restrict__ split_rows,
     int n_orphan, const double* __restrict__ partials, DevScalars* __restrict__ sc, int pcg_mode, int nb_hot,
-    int nb_cold) {
+    int nb_cold, const double* __restrict__ bt_rows, int n_partials) {
+  // between-factor part of camera entry i = 9 c + k (k < 6), if any
+  auto between_part = [&](int64_t i) -> double {
+    const int k = (int)(i % 9);
+    return (bt_rows != nullptr && k < 6) ? bt_rows[(i / 9) * 6 + k] : 0.0;
+  };
   __shared__ double red[4][64];
   if (pcg_mode && sc->done) return;
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
@@ -456,7 +461,7 @@ __global__ __launch_bounds__(256) void k_matvec_final(
       double tot = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) tot += gsum[k][cl];
-      w[col] = (S)fma(lambda * (double)D[col], (double)p[col], tot);
+      w[col] = (S)fma(lambda * (double)D[col], (double)p[col], tot + between_part(col));
     }
   } else if (b < nb_hot + nb_cold) {
     const int c = K + (b - nb_hot) * 4 + grp;
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(256) void k_matvec_final(
         const double tot = wave_sum(acc[k]);
         if (lane == 0) {
           const size_t i = 9 * (size_t)c + k;
-          w[i] = (S)fma(lambda * (double)D[i], (double)p[i], tot);
+          w[i] = (S)fma(lambda * (double)D[i], (double)p[i], tot + between_part((int64_t)i));
         }
       }
     }
@@ -503,7 +508,7 @@ __global__ __launch_bounds__(256) void k_matvec_final(
   }
   if (b == 0) {
     double s = 0.0;
-    for (int g = tid; g < G; g += blockDim.x) s += partials[(size_t)g * kPartialWidth];
+    for (int g = tid; g < n_partials; g += blockDim.x) s += partials[(size_t)g * kPartialWidth];
     s = block_sum(s, &red[0][0]);
     if (tid == 0) {
       sc->pAp = s;
@@ -555,6 +560,9 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
     else
       launch_matvec<S, false>(h, lambda, p, w, scp);
   }
+  // pose between-factors: their share of the camera rows and of p^T A p
+  run_between_product(h, p, pcg_mode);
+  const int n_partials = h->G + (h->n_between > 0 ? (int)between_grid(h) : 0);
   const int nb_hot = (h->K * 9 + kHotCols - 1) / kHotCols;
   const int nb_cold = (h->nc - h->K + 3) / 4;
   const int64_t nrest = 3 * (int64_t)h->n_split_pts + 3 * (int64_t)h->n_orphan_pts;
@@ -565,7 +573,7 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
                                           h->cold_list, p,
                                           (const S*)h->vec.D, lambda, w, h->n_split_pts, h->split_pts,
                                           h->split_rows, h->n_orphan_pts, h->partials, h->scal, pcg_mode ? 1 : 0,
-                                          nb_hot, nb_cold);
+                                          nb_hot, nb_cold, h->n_between > 0 ? h->bt_rows : nullptr, n_partials);
   CBA_LAUNCHED();
 }
 

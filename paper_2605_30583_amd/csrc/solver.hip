@@ -496,6 +496,9 @@ int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad
   check_device(h);
   ensure_linearized(h);
   CBA_REQUIRE((flags & ~CASPAR_ADJ_GAUGE_PROJECT) == 0, "unknown backward flags");
+  CBA_REQUIRE(!(flags & CASPAR_ADJ_GAUGE_PROJECT) || h->n_between == 0,
+              "gauge projection removes the similarity gauge of reprojection-only problems; "
+              "pose between-factors fix the scale");
   if (h->prec == CASPAR_FP64)
     adjoint_rhs_t<double>(h, grad_cams, grad_points);
   else
