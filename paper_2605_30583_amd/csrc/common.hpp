@@ -139,7 +139,8 @@ struct DevScalars {
   // [3] absmax, [4..6] predicted-decrease dots, [7] between-factor r.r
   double red[8];
   int err;
-  int pad1[3];
+  int last_x;  // the iteration that set `done` made a valid update whose x step is still due
+  int pad1[2];
 };
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXITER = 3, PCG_ZERO_RHS = 4 };
 

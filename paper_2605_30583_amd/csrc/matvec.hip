@@ -155,7 +155,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows,
-    double* __restrict__ partials, const DevScalars* __restrict__ sc, int P, int L, int local_base,
+    double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L, int local_base,
     unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
   constexpr int THREADS = MvCfg<S, RJ>::threads;
   constexpr int WAVES = THREADS / kWave;
@@ -173,7 +173,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   double* win = priv + (size_t)kPrivCopies * P * 9;        // [L][9]
   const int lo = L > 0 ? cold_lo[blockIdx.x] : 0;
   __shared__ double red[WAVES];
-  if (sc != nullptr && sc->done) return;
+  if (sc != nullptr && sc->done) {
+    // the iteration after the one that stopped PCG: its x step has been taken
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->last_x = 0;
+    return;
+  }
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
@@ -526,7 +530,7 @@ __global__ __launch_bounds__(256) void k_matvec_final(
 }
 
 template <typename S, bool RJ>
-static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const DevScalars* scp) {
+static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScalars* scp) {
   constexpr int T = MvCfg<S, RJ>::threads;
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = matvec_lds_bytes(h->K, h->L);
@@ -548,7 +552,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, const D
 template <typename S>
 static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mode, bool pad_cams) {
   hipStream_t st = h->stream;
-  const DevScalars* scp = pcg_mode ? h->scal : nullptr;
+  DevScalars* scp = pcg_mode ? h->scal : nullptr;
   if (h->n_tiles > 0 || h->nc > 0 || h->n_orphan_pts > 0) {
     if (pad_cams) {
       k_pad_cams<S><<<(unsigned)std::max(1, (h->nc + 255) / 256), 256, 0, st>>>(

@@ -188,6 +188,7 @@ __global__ void k_pcg_scalar0(int n, const double* __restrict__ partials, double
     sc->beta = 0.0;
     sc->done = 0;
     sc->reason = PCG_RUNNING;
+    sc->last_x = 0;
     if (c == 0.0) {
       sc->done = 1;
       sc->reason = PCG_ZERO_RHS;
@@ -199,7 +200,9 @@ __global__ void k_pcg_scalar0(int n, const double* __restrict__ partials, double
 }
 
 // x += alpha p; r -= alpha w; z = M^-1 r; partials: r^T r, r^T z.
-// Stop test and beta after an update, from |r|^2 (a) and r^T z (c).
+// Stop test and beta after an update, from |r|^2 (a) and r^T z (c).  Any
+// stop set here follows a completed update of r, so its x step (applied by
+// the direction kernel) is still due: last_x.
 __device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double c) {
   sc->rr = a;
   if (!isfinite(a) || !isfinite(c)) {
@@ -216,17 +219,18 @@ __device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double
       sc->reason = PCG_MAXITER;
     }
   }
+  sc->last_x = sc->done;
 }
 
-// x += alpha p, r -= alpha w, z = M^-1 r, and the sums r^T r, r^T z.  Thread
-// i takes camera block i and point block i (grid-stride), each with its
-// whole block in registers (vector loads of 3 or 9 consecutive values).
-// Workgroup sums go to the partial slots.
+// r -= alpha w, z = M^-1 r, and the sums r^T r, r^T z.  Thread i takes
+// camera block i and point block i (grid-stride), each with its whole block
+// in registers (vector loads of 3 or 9 consecutive values).  Workgroup sums
+// go to the partial slots.  The x step of the same iteration is taken by the
+// direction kernel, which reads p anyway.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __restrict__ Mc,
-                                                    const S* __restrict__ Mp, S* __restrict__ x,
-                                                    S* __restrict__ r, S* __restrict__ z,
-                                                    const S* __restrict__ p, const S* __restrict__ w,
+                                                    const S* __restrict__ Mp, S* __restrict__ r,
+                                                    S* __restrict__ z, const S* __restrict__ w,
                                                     const DevScalars* __restrict__ sc,
                                                     double* __restrict__ partials) {
   __shared__ double red[4];
@@ -237,40 +241,32 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t c = i0; c < nc; c += stride) {
     const size_t o = 9 * (size_t)c;
-    S pv[9], wv[9], xv[9], rv[9];
+    S wv[9], rv[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      pv[k] = p[o + k];
       wv[k] = w[o + k];
-      xv[k] = x[o + k];
       rv[k] = r[o + k];
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      x[o + k] = (S)fma(alpha, (double)pv[k], (double)xv[k]);
       rv[k] = (S)fma(-alpha, (double)wv[k], (double)rv[k]);
       r[o + k] = rv[k];
     }
     block_apply<S, 9>(Mc + 45 * c, rv, z + o, rz, rr);
   }
-  const S* __restrict__ pp = p + 9 * (size_t)nc;
   const S* __restrict__ wp = w + 9 * (size_t)nc;
-  S* __restrict__ xp = x + 9 * (size_t)nc;
   S* __restrict__ rp = r + 9 * (size_t)nc;
   S* __restrict__ zp = z + 9 * (size_t)nc;
   for (int64_t i = i0; i < np; i += stride) {
     const size_t o = 3 * (size_t)i;
-    S pv[3], wv[3], xv[3], rv[3];
+    S wv[3], rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      pv[k] = pp[o + k];
       wv[k] = wp[o + k];
-      xv[k] = xp[o + k];
       rv[k] = rp[o + k];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      xp[o + k] = (S)fma(alpha, (double)pv[k], (double)xv[k]);
       rv[k] = (S)fma(-alpha, (double)wv[k], (double)rv[k]);
       rp[o + k] = rv[k];
     }
@@ -301,15 +297,20 @@ __global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevSca
   if (threadIdx.x == 0) pcg_scalars_after_update(sc, a, c);
 }
 
-// p = z + beta p, four elements per thread with 16-byte vector accesses;
-// the camera part is also written to the padded camera rows that the next
-// product gathers from.
+// The iteration's x step x += alpha p with the current p, then the new
+// direction p = z + beta p unless the iteration stopped the solve; four
+// elements per thread with 16-byte vector accesses.  The camera part of p
+// is also written to the camera rows that the next product gathers from.
+// A solve stopped by an earlier iteration (or by the product's breakdown
+// test, before any update) leaves x alone.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_p(int64_t N, int nc, const S* __restrict__ z, S* __restrict__ p,
-                                               S* __restrict__ p_cam, int row_stride, int row_off,
-                                               const DevScalars* __restrict__ sc) {
+                                               S* __restrict__ x, S* __restrict__ p_cam, int row_stride,
+                                               int row_off, const DevScalars* __restrict__ sc) {
   using V = S __attribute__((ext_vector_type(4)));
-  if (sc->done) return;
+  if (sc->done && !sc->last_x) return;
+  const bool new_dir = !sc->done;
+  const double alpha = sc->alpha;
   const double beta = sc->beta;
   const int64_t ncam = 9 * (int64_t)nc;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -320,22 +321,34 @@ __global__ __launch_bounds__(256) void k_pcg_p(int64_t N, int nc, const S* __res
   const int64_t n4 = N / 4;
   const V* __restrict__ z4 = reinterpret_cast<const V*>(z);
   V* __restrict__ p4 = reinterpret_cast<V*>(p);
+  V* __restrict__ x4 = reinterpret_cast<V*>(x);
   for (int64_t q = i0; q < n4; q += stride) {
-    const V zv = z4[q];
     const V pv = p4[q];
-    V o;
+    const V xv = x4[q];
+    V xo;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = (S)fma(beta, (double)pv[k], (double)zv[k]);
-    p4[q] = o;
-    if (4 * q < ncam) {
+    for (int k = 0; k < 4; ++k) xo[k] = (S)fma(alpha, (double)pv[k], (double)xv[k]);
+    x4[q] = xo;
+    if (new_dir) {
+      const V zv = z4[q];
+      V o;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) to_row(4 * q + k, o[k]);
+      for (int k = 0; k < 4; ++k) o[k] = (S)fma(beta, (double)pv[k], (double)zv[k]);
+      p4[q] = o;
+      if (4 * q < ncam) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) to_row(4 * q + k, o[k]);
+      }
     }
   }
   for (int64_t e = 4 * n4 + i0; e < N; e += stride) {
-    const S o = (S)fma(beta, (double)p[e], (double)z[e]);
-    p[e] = o;
-    to_row(e, o);
+    const S pe = p[e];
+    x[e] = (S)fma(alpha, (double)pe, (double)x[e]);
+    if (new_dir) {
+      const S o = (S)fma(beta, (double)pe, (double)z[e]);
+      p[e] = o;
+      to_row(e, o);
+    }
   }
 }
 
@@ -512,11 +525,12 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
       // the first product pads the camera rows of p itself; later ones use
       // the rows written by k_pcg_p
       run_matvec(h, lambda, p, w, true, launched + k == 0);
-      k_pcg_update<S><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, x, r, z, p, w, h->scal, h->partials);
+      k_pcg_update<S><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, r, z, w, h->scal, h->partials);
       CBA_LAUNCHED();
       k_pcg_scalar1<<<1, 1024, 0, st>>>((int)ug, h->partials, h->scal);
       CBA_LAUNCHED();
-      k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, (S*)h->p_cam, cam_row_stride<S>(h), cam_row_p_off(h), h->scal);
+      k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, x, (S*)h->p_cam, cam_row_stride<S>(h), cam_row_p_off(h),
+                                     h->scal);
       CBA_LAUNCHED();
     }
     launched += check_every;
