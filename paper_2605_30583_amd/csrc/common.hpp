@@ -215,6 +215,8 @@ struct caspar_ba {
   int* cm_obs = nullptr;        // [no] internal observation of each camera-major entry
   int* cm_pt = nullptr;         // [no] internal point of each camera-major entry
   double* cm_px = nullptr;      // [no][2]
+  void* px_s = nullptr;         // [no][2] float32 copy of px (float32-mixed form)
+  void* cm_px_s = nullptr;      // [no][2] float32 copy of cm_px (float32-mixed form)
   int* cam_off = nullptr;       // [nc + 1]
   cba::Chunk* chunks = nullptr;
   int* chunk_off = nullptr;     // [nc + 1] chunks of camera c
@@ -272,7 +274,7 @@ struct Plan {
   struct Region {
     size_t off = 0, bytes = 0;
   };
-  Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
+  Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, px_s, cm_px_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
   size_t vec_bytes = 0;
@@ -296,6 +298,27 @@ inline int cam_row_stride(const caspar_ba* h) {
   return h->rj ? kProdCamRow : CamPad<S>::n;
 }
 inline int cam_row_p_off(const caspar_ba* h) { return h->rj ? kProdCamP : 0; }
+
+// Observed pixels in the working precision (the float32 kernels use them
+// only as float32): point-major and camera-major.
+template <typename S>
+inline const S* pixels_of(const caspar_ba* h) {
+  return static_cast<const S*>(sizeof(S) == 4 ? h->px_s : static_cast<const void*>(h->px));
+}
+template <typename S>
+inline const S* cm_pixels_of(const caspar_ba* h) {
+  return static_cast<const S*>(sizeof(S) == 4 ? h->cm_px_s : static_cast<const void*>(h->cm_px));
+}
+template <typename S>
+struct Pair;
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <>
+struct Pair<double> {
+  using type = double2;
+};
 
 // Points in the working precision: the float32 copy written at each
 // linearisation, or the (current) float64 master rows.

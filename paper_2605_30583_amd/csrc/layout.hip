@@ -105,6 +105,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.obs_s2c, (size_t)no * 4);
   take(p.meta, no_pad * 4);
   take(p.px, (size_t)no * 16);
+  take(p.px_s, prec == CASPAR_FP64 ? 16 : (size_t)no * 8);
   // J doubles as the create-time scratch (sort buffers, counters).
   const size_t scratch = 2 * 8 * (size_t)no + 2 * 4 * (size_t)no + 4 * (size_t)no +
                          align_up(sort_bytes) + 8 * (size_t)np + 8 * (size_t)nc + 8192;
@@ -114,6 +115,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.p_cam, (size_t)nc * kProdCamRow * 8);
   take(p.cm_pt, (size_t)no * 4);
   take(p.cm_px, (size_t)no * 16);
+  take(p.cm_px_s, prec == CASPAR_FP64 ? 16 : (size_t)no * 8);
   take(p.cam_off, ((size_t)nc + 1) * 4);
   take(p.chunks, p.max_chunks * sizeof(Chunk));
   take(p.chunk_off, ((size_t)nc + 1) * 4);
@@ -262,6 +264,18 @@ __global__ void k_points_out(int np, const double* __restrict__ X, const int* __
   for (int k = 0; k < 3; ++k) out[3 * (size_t)p + k] = X[3 * (size_t)q + k];
 }
 
+// float32 copies of both pixel orders (float32-mixed form).
+__global__ void k_px_cast(int64_t n, const double2* __restrict__ a, const double2* __restrict__ b,
+                          float2* __restrict__ as, float2* __restrict__ bs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 u = a[i], v = b[i];
+    as[i] = make_float2((float)u.x, (float)u.y);
+    bs[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+
 __global__ void k_set_px(int no, const int* __restrict__ s2c, const double* __restrict__ px_caller,
                          double* px) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,6 +318,15 @@ __global__ void k_project(int64_t no, const double* __restrict__ cams, const dou
 
 static inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
+}
+
+static void cast_pixels(caspar_ba* h) {
+  if (h->prec == CASPAR_FP64 || h->no == 0) return;
+  k_px_cast<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, reinterpret_cast<const double2*>(h->px),
+                                                           reinterpret_cast<const double2*>(h->cm_px),
+                                                           static_cast<float2*>(h->px_s),
+                                                           static_cast<float2*>(h->cm_px_s));
+  CBA_LAUNCHED();
 }
 
 void sync(caspar_ba* h) { CBA_HIP(hipStreamSynchronize(h->stream)); }
@@ -495,6 +518,7 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
                                                vals_a, cm_obs, no, 0, cam_bits, st));
     k_fill_cm<<<blocks_for(no, 256), 256, 0, st>>>(no, cm_obs, keys_b, h->px, h->cm_pt, h->cm_px);
     CBA_LAUNCHED();
+    cast_pixels(h);
   }
 
   // Camera offsets (internal order) and linearisation chunks.
@@ -704,6 +728,8 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     h->cm_obs = (int*)(ws + plan.cm_obs.off);
     h->cm_pt = (int*)(ws + plan.cm_pt.off);
     h->cm_px = (double*)(ws + plan.cm_px.off);
+    h->px_s = ws + plan.px_s.off;
+    h->cm_px_s = ws + plan.cm_px_s.off;
     h->cam_off = (int*)(ws + plan.cam_off.off);
     h->chunks = (Chunk*)(ws + plan.chunks.off);
     h->chunk_off = (int*)(ws + plan.chunk_off.off);
@@ -783,6 +809,7 @@ int caspar_ba_set_observations(caspar_ba* h, const double* obs_px) {
     CBA_LAUNCHED();
     k_set_cm_px<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->cm_obs, h->px, h->cm_px);
     CBA_LAUNCHED();
+    cast_pixels(h);
   }
   h->linearized = false;
   sync(h);

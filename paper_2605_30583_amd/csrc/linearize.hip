@@ -84,7 +84,7 @@ __global__ void k_point_cast(int np, const double* __restrict__ X, float4* __res
 template <typename S, bool STORE_J>
 __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __restrict__ tiles,
                                                     const uint32_t* __restrict__ meta,
-                                                    const double* __restrict__ px,
+                                                    const S* __restrict__ px,
                                                     const S* __restrict__ camtab,
                                                     const S* __restrict__ pts, void* J,
                                                     S* __restrict__ g, S* __restrict__ D,
@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
   // One tile from its loaded inputs: residual, blocks (stored if STORE_J),
   // cost, and per point the segmented sums of g_p and the upper triangle of
   // H_p, written by the point's first lane.
-  auto tile = [&](const Tile& tl, int n, uint32_t m, const Cam<S>& c, const S (&Xp)[3], double2 q, int o) {
+  using P2 = typename Pair<S>::type;
+  auto tile = [&](const Tile& tl, int n, uint32_t m, const Cam<S>& c, const S (&Xp)[3], P2 q, int o) {
     const bool act = lane < n;
     const int lp = act ? (int)(m >> kCamBits) : 100 + lane;
     double v[9];
@@ -193,8 +194,8 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
     S xa[3], xb[3];
     load_point<S>(pts, (size_t)(ta.pt_begin + (int)(ma >> kCamBits)), xa);
     load_point<S>(pts, (size_t)(tb.pt_begin + (int)(mb >> kCamBits)), xb);
-    const double2 qa = reinterpret_cast<const double2*>(px)[oa];
-    const double2 qb = reinterpret_cast<const double2*>(px)[ob];
+    const P2 qa = reinterpret_cast<const P2*>(px)[oa];
+    const P2 qb = reinterpret_cast<const P2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
     tile(ta, na, ma, ca, xa, qa, oa);
     if (t2 < n_tiles) tile(tb, nb, mb, cb, xb, qb, ob);
@@ -279,7 +280,7 @@ __device__ inline int wave_scatter54(double* v, int lane) {
 template <typename S>
 __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chunks,
                                                   const int* __restrict__ cm_pt,
-                                                  const double* __restrict__ cm_px,
+                                                  const S* __restrict__ cm_px,
                                                   const double* __restrict__ cam,
                                                   const S* __restrict__ pts,
                                                   double* __restrict__ rows, int loss, double loss_c) {
@@ -289,13 +290,14 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
   const int tid = threadIdx.x;
   int jj[kPer];
   S xp[kPer][3];
-  double2 q[kPer];
+  using P2 = typename Pair<S>::type;
+  P2 q[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) jj[i] = cm_pt[min(ch.begin + tid + 256 * i, ch.end - 1)];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     load_point<S>(pts, (size_t)jj[i], xp[i]);
-    q[i] = reinterpret_cast<const double2*>(cm_px)[min(ch.begin + tid + 256 * i, ch.end - 1)];
+    q[i] = reinterpret_cast<const P2*>(cm_px)[min(ch.begin + tid + 256 * i, ch.end - 1)];
   }
   const Cam<S> c = load_cam<S>(cam, ch.cam);
   double acc[kCamRowWidth];
@@ -394,7 +396,7 @@ __global__ void k_sum_partials(int n, const double* __restrict__ partials, int c
 template <typename S>
 __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restrict__ tiles,
                                               const uint32_t* __restrict__ meta,
-                                              const double* __restrict__ px,
+                                              const S* __restrict__ px,
                                               const S* __restrict__ camtab,
                                               const double* __restrict__ X,
                                               double* __restrict__ partials, int loss, double loss_c) {
@@ -423,8 +425,9 @@ __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restric
     const double* Xa = X + 3 * (size_t)(ta.pt_begin + (int)(ma >> kCamBits));
     const double* Xb = X + 3 * (size_t)(tb.pt_begin + (int)(mb >> kCamBits));
     const double xa[3] = {Xa[0], Xa[1], Xa[2]}, xb[3] = {Xb[0], Xb[1], Xb[2]};
-    const double2 qa = reinterpret_cast<const double2*>(px)[oa];
-    const double2 qb = reinterpret_cast<const double2*>(px)[ob];
+    using P2 = typename Pair<S>::type;
+    const P2 qa = reinterpret_cast<const P2*>(px)[oa];
+    const P2 qb = reinterpret_cast<const P2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
     // rho(|r|^2) of one observation (|r|^2 with the trivial loss)
     auto term = [&](S r0, S r1) {
@@ -564,11 +567,11 @@ static void linearize_t(caspar_ba* h) {
   const S* ptab = (const S*)pts_table(h);
   if (h->n_tiles > 0) {
     if (h->rj)
-      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
+      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<S>(h), camtab, ptab, h->J, g, D,
                                                  h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
                                                  (S*)h->wts);
     else
-      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, camtab, ptab, h->J, g, D,
+      k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<S>(h), camtab, ptab, h->J, g, D,
                                                 h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
                                                  (S*)h->wts);
     CBA_LAUNCHED();
@@ -587,7 +590,7 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->n_chunks > 0) {
-    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, h->cm_px, h->cam, ptab, h->chunk_rows,
+    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, cm_pixels_of<S>(h), h->cam, ptab, h->chunk_rows,
                                                h->loss, h->loss_c);
     CBA_LAUNCHED();
   }
@@ -617,7 +620,7 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
   const bool f64 = fp64 || h->prec == CASPAR_FP64;
   const unsigned tg = f64 ? tile_grid<k_cost<double>>(h->n_tiles) : tile_grid<k_cost<float>>(h->n_tiles);
   if (f64) {
-    k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, cam, X, h->partials, h->loss,
+    k_cost<double><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<double>(h), cam, X, h->partials, h->loss,
                                        h->loss_c);
   } else {
     // float32 rows of the cameras being evaluated, so the residual kernel
@@ -625,7 +628,7 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
     k_cam_cast<float><<<nblk((int64_t)h->nc * kCamStride, 256), 256, 0, st>>>(h->nc * kCamStride, cam,
                                                                               (float*)h->cam_trial_s);
     CBA_LAUNCHED();
-    k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, h->px, (const float*)h->cam_trial_s, X,
+    k_cost<float><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<float>(h), (const float*)h->cam_trial_s, X,
                                       h->partials, h->loss, h->loss_c);
   }
   CBA_LAUNCHED();
