@@ -14,10 +14,11 @@
 // The calibration columns are zero.
 //
 // Each camera gathers its incident factors through a host-built incidence
-// list (the pairwise read: both cameras of a factor), evaluates them in
-// float64 and adds its own side's share (the pairwise add, with no atomics:
-// every factor is evaluated once per endpoint).  Factors are few (about one
-// per camera), so the kernels are small beside the reprojection work.
+// list (the pairwise read: both cameras of a factor) and adds its own side's
+// share (the pairwise add, with no atomics).  The linearisation evaluates
+// every factor in float64 at both endpoints and keeps its blocks; each
+// product applies the kept blocks.  Factors are few (about one per camera),
+// so the kernels are small beside the reprojection work.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -27,6 +28,11 @@
 #include "model.hpp"
 
 namespace cba {
+
+// Blocks of a factor kept from the linearisation for the products: with
+// Ji = [[-A, 0], [-B, -C]] and Jj = [[A, 0], [B, s_trans I]] only A, B, C
+// (row-major) and s_trans are stored.
+constexpr int kBetweenBlock = 28;
 
 // Residual (and with BLOCKS the two 6x6 blocks, columns [dw, dt]) of factor
 // F at the float64 camera rows.
@@ -114,11 +120,11 @@ __device__ inline void between_eval(const BetweenFactor& F, const double* __rest
 // the updated diagonal.  Partials: sum of r.r, each factor counted at its
 // first camera.  Runs after the reprojection sums are in g, H_cc and D.
 template <typename S>
-__global__ __launch_bounds__(256) void k_between_lin(int nc, const double* __restrict__ cam,
+__global__ __launch_bounds__(64) void k_between_lin(int nc, const double* __restrict__ cam,
                                                      const BetweenFactor* __restrict__ fac,
                                                      const int* __restrict__ off, const int* __restrict__ inc,
                                                      S* __restrict__ g, S* __restrict__ D, double* __restrict__ Hcc,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ blocks, double* __restrict__ partials) {
   __shared__ double red[4];
   double rr = 0.0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
@@ -133,7 +139,20 @@ __global__ __launch_bounds__(256) void k_between_lin(int nc, const double* __res
       double r[6], Ji[6][6], Jj[6][6];
       between_eval<true>(F, cam, r, Ji, Jj);
       const bool second = (e & 1) != 0;
-      if (!second) rr += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3] + r[4] * r[4] + r[5] * r[5];
+      if (!second) {
+        rr += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3] + r[4] * r[4] + r[5] * r[5];
+        // the factor's blocks for the products, written once (first camera)
+        double* bl = blocks + (size_t)(e >> 1) * kBetweenBlock;
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) {
+            bl[3 * x + y] = Jj[x][y];
+            bl[9 + 3 * x + y] = Jj[3 + x][y];
+            bl[18 + 3 * x + y] = -Ji[3 + x][3 + y];
+          }
+        bl[27] = F.s_trans;
+      }
       int t = 0;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
@@ -181,9 +200,13 @@ __global__ __launch_bounds__(256) void k_between_cost(int nf, const double* __re
 // Product: per camera, rows[c] = sum over its factors of J_c^T (J_i p_i + J_j p_j)
 // (the [dw, dt] part; the final product kernel adds it to w), and the
 // partials of |J_i p_i + J_j p_j|^2, each factor counted at its first camera.
+// With the stored A, B, C: q_rot = A (w_j - w_i), q_trans = B (w_j - w_i) -
+// C t_i + s_trans t_j for the [dw, dt] parts w, t of p; the first camera
+// takes (-A^T q_rot - B^T q_trans, -C^T q_trans), the second
+// (A^T q_rot + B^T q_trans, s_trans q_trans).
 template <typename S>
-__global__ __launch_bounds__(256) void k_between_product(int nc, const double* __restrict__ cam,
-                                                         const BetweenFactor* __restrict__ fac,
+__global__ __launch_bounds__(64) void k_between_product(int nc, const BetweenFactor* __restrict__ fac,
+                                                         const double* __restrict__ blocks,
                                                          const int* __restrict__ off, const int* __restrict__ inc,
                                                          const S* __restrict__ p, double* __restrict__ rows,
                                                          double* __restrict__ partials,
@@ -195,30 +218,34 @@ __global__ __launch_bounds__(256) void k_between_product(int nc, const double* _
     double w6[6] = {0, 0, 0, 0, 0, 0};
     for (int q = off[c]; q < off[c + 1]; ++q) {
       const int e = inc[q];
-      const BetweenFactor F = fac[e >> 1];
-      double r[6], Ji[6][6], Jj[6][6];
-      between_eval<true>(F, cam, r, Ji, Jj);
-      double pi[6], pj[6];
+      const int f = e >> 1;
+      const int ci = fac[f].ci, cj = fac[f].cj;
+      const double* bl = blocks + (size_t)f * kBetweenBlock;
+      double dw[3], ti[3], tj[3];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        pi[k] = (double)p[9 * (size_t)F.ci + k];
-        pj[k] = (double)p[9 * (size_t)F.cj + k];
+      for (int k = 0; k < 3; ++k) {
+        dw[k] = (double)p[9 * (size_t)cj + k] - (double)p[9 * (size_t)ci + k];
+        ti[k] = (double)p[9 * (size_t)ci + 3 + k];
+        tj[k] = (double)p[9 * (size_t)cj + 3 + k];
       }
-      double qv[6];
+      const double st = bl[27];
+      double qr[3], qt[3];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s += Ji[a][k] * pi[k] + Jj[a][k] * pj[k];
-        qv[a] = s;
+      for (int x = 0; x < 3; ++x) {
+        qr[x] = bl[3 * x] * dw[0] + bl[3 * x + 1] * dw[1] + bl[3 * x + 2] * dw[2];
+        qt[x] = bl[9 + 3 * x] * dw[0] + bl[9 + 3 * x + 1] * dw[1] + bl[9 + 3 * x + 2] * dw[2] -
+                (bl[18 + 3 * x] * ti[0] + bl[18 + 3 * x + 1] * ti[1] + bl[18 + 3 * x + 2] * ti[2]) + st * tj[x];
       }
       const bool second = (e & 1) != 0;
-      if (!second)
-        pap += qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3] + qv[4] * qv[4] + qv[5] * qv[5];
+      if (!second) pap += qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qt[0] * qt[0] + qt[1] * qt[1] + qt[2] * qt[2];
+      const double sg = second ? 1.0 : -1.0;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-#pragma unroll
-        for (int a = 0; a < 6; ++a) w6[k] += (second ? Jj[a][k] : Ji[a][k]) * qv[a];
+      for (int y = 0; y < 3; ++y) {
+        const double aq = bl[y] * qr[0] + bl[3 + y] * qr[1] + bl[6 + y] * qr[2];
+        const double bq = bl[9 + y] * qt[0] + bl[12 + y] * qt[1] + bl[15 + y] * qt[2];
+        const double cq = bl[18 + y] * qt[0] + bl[21 + y] * qt[1] + bl[24 + y] * qt[2];
+        w6[y] += sg * (aq + bq);
+        w6[3 + y] += second ? st * qt[y] : -cq;
       }
     }
 #pragma unroll
@@ -236,19 +263,25 @@ __global__ void k_between_sum(int n, const double* __restrict__ partials, DevSca
   if (threadIdx.x == 0) sc->red[slot] = s;
 }
 
+// One wave per workgroup: a camera's factors run one after another in its
+// thread, so the cameras are spread over as many CUs as there are waves.
+constexpr int kBetweenThreads = 64;
+
 unsigned between_grid(const caspar_ba* h) {
-  return (unsigned)std::max(1, std::min((h->nc + 255) / 256, 1024));
+  return (unsigned)std::max(1, std::min((h->nc + kBetweenThreads - 1) / kBetweenThreads, 1024));
 }
 
 void run_between_lin(caspar_ba* h) {
   if (h->n_between == 0) return;
   const unsigned g = between_grid(h);
   if (h->prec == CASPAR_FP64)
-    k_between_lin<double><<<g, 256, 0, h->stream>>>(h->nc, h->cam, h->between, h->bt_off, h->bt_inc,
-                                                   (double*)h->vec.g, (double*)h->vec.D, h->Hcc, h->partials);
+    k_between_lin<double><<<g, kBetweenThreads, 0, h->stream>>>(h->nc, h->cam, h->between, h->bt_off, h->bt_inc,
+                                                   (double*)h->vec.g, (double*)h->vec.D, h->Hcc, h->bt_blocks,
+                                                   h->partials);
   else
-    k_between_lin<float><<<g, 256, 0, h->stream>>>(h->nc, h->cam, h->between, h->bt_off, h->bt_inc,
-                                                  (float*)h->vec.g, (float*)h->vec.D, h->Hcc, h->partials);
+    k_between_lin<float><<<g, kBetweenThreads, 0, h->stream>>>(h->nc, h->cam, h->between, h->bt_off, h->bt_inc,
+                                                  (float*)h->vec.g, (float*)h->vec.D, h->Hcc, h->bt_blocks,
+                                                  h->partials);
   CBA_LAUNCHED();
   k_between_sum<<<1, 1024, 0, h->stream>>>((int)g, h->partials, h->scal, 7);
   CBA_LAUNCHED();
@@ -270,11 +303,11 @@ void run_between_product(caspar_ba* h, const void* p, bool pcg_mode) {
   // partial slots after the fused product's G workgroup slots
   double* part = h->partials + (size_t)h->G * kPartialWidth;
   if (h->prec == CASPAR_FP64)
-    k_between_product<double><<<between_grid(h), 256, 0, h->stream>>>(
-        h->nc, h->cam, h->between, h->bt_off, h->bt_inc, (const double*)p, h->bt_rows, part, scp);
+    k_between_product<double><<<between_grid(h), kBetweenThreads, 0, h->stream>>>(
+        h->nc, h->between, h->bt_blocks, h->bt_off, h->bt_inc, (const double*)p, h->bt_rows, part, scp);
   else
-    k_between_product<float><<<between_grid(h), 256, 0, h->stream>>>(
-        h->nc, h->cam, h->between, h->bt_off, h->bt_inc, (const float*)p, h->bt_rows, part, scp);
+    k_between_product<float><<<between_grid(h), kBetweenThreads, 0, h->stream>>>(
+        h->nc, h->between, h->bt_blocks, h->bt_off, h->bt_inc, (const float*)p, h->bt_rows, part, scp);
   CBA_LAUNCHED();
 }
 
@@ -283,7 +316,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct BetweenPlan {
-  size_t fac, off, inc, rows, total;
+  size_t fac, off, inc, rows, blocks, total;
 };
 
 BetweenPlan between_plan(int64_t n, int64_t nc) {
@@ -297,6 +330,8 @@ BetweenPlan between_plan(int64_t n, int64_t nc) {
   o += align256((size_t)(2 * n) * sizeof(int));
   p.rows = o;
   o += align256((size_t)nc * 6 * sizeof(double));
+  p.blocks = o;
+  o += align256((size_t)n * kBetweenBlock * sizeof(double));
   p.total = o;
   return p;
 }
@@ -357,6 +392,7 @@ int caspar_ba_set_between(caspar_ba* h, int32_t n_factors, const int32_t* cam_i,
     h->between = nullptr;
     h->bt_off = h->bt_inc = nullptr;
     h->bt_rows = nullptr;
+    h->bt_blocks = nullptr;
     h->linearized = false;
     h->bj_lambda = -1.0;
     return CASPAR_OK;
@@ -412,6 +448,7 @@ int caspar_ba_set_between(caspar_ba* h, int32_t n_factors, const int32_t* cam_i,
   h->bt_off = reinterpret_cast<int*>(ws + plan.off);
   h->bt_inc = reinterpret_cast<int*>(ws + plan.inc);
   h->bt_rows = reinterpret_cast<double*>(ws + plan.rows);
+  h->bt_blocks = reinterpret_cast<double*>(ws + plan.blocks);
   h->linearized = false;
   h->bj_lambda = -1.0;
   CBA_API_END

@@ -247,6 +247,7 @@ struct caspar_ba {
   int* bt_off = nullptr;        // [nc + 1] incident factors of each internal camera
   int* bt_inc = nullptr;        // [2 n_between] factor * 2 + side (0: first camera, 1: second)
   double* bt_rows = nullptr;    // [nc][6] between part of the product's camera rows
+  double* bt_blocks = nullptr;  // [n_between][kBetweenBlock] blocks at the last linearisation
 
   double* partials = nullptr;   // [kMaxPartials][4]
   double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
