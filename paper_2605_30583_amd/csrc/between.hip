@@ -287,13 +287,18 @@ void run_between_lin(caspar_ba* h) {
   CBA_LAUNCHED();
 }
 
-double run_between_cost(caspar_ba* h, const double* cam) {
-  if (h->n_between == 0) return 0.0;
+void launch_between_cost(caspar_ba* h, const double* cam) {
+  if (h->n_between == 0) return;
   const unsigned g = (unsigned)std::max(1, std::min((h->n_between + 255) / 256, 1024));
   k_between_cost<<<g, 256, 0, h->stream>>>(h->n_between, cam, h->between, h->partials);
   CBA_LAUNCHED();
   k_between_sum<<<1, 1024, 0, h->stream>>>((int)g, h->partials, h->scal, 7);
   CBA_LAUNCHED();
+}
+
+double run_between_cost(caspar_ba* h, const double* cam) {
+  if (h->n_between == 0) return 0.0;
+  launch_between_cost(h, cam);
   return 0.5 * read_scalars(h).red[7];
 }
 

@@ -346,6 +346,8 @@ void upload_points(caspar_ba* h, const double* pts_caller, double* X_internal);
 // linearize.hip
 void run_linearize(caspar_ba* h);                   // J, g, H, D, cost, gmax
 double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  // F at params
+void launch_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  // its sums, no read-back
+double cost_of(const caspar_ba* h, const DevScalars& s);  // F from the sums launch_cost left
 void run_retract(caspar_ba* h, const void* delta);  // trial = current (+) delta
 void run_export_linearization(caspar_ba* h, double* resid, double* jc, double* jp);
 // matvec.hip
@@ -357,7 +359,10 @@ int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double to
             int check_every, void* x, double* rel_resid);
 double run_dot(caspar_ba* h, const void* a, const void* b, const void* wdiag);  // sum a b (w)
 void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx);  // g^T x, x^T r, x^T D x
+void launch_pred_dots(caspar_ba* h);                // the same into red[4..6], no read-back
+void pred_dots_of(const caspar_ba* h, const DevScalars& s, double* gx, double* xr, double* xDx);
 double run_absmax(caspar_ba* h, const void* a);
+void launch_absmax(caspar_ba* h, const void* a);    // max |a| into red[3], no read-back
 void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
 void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);
 void run_zero(caspar_ba* h, void* v, size_t count_scalars);
@@ -368,6 +373,7 @@ double matvec_algorithmic_bytes(const caspar_ba* h);
 // between.hip
 void run_between_lin(caspar_ba* h);                 // adds g, H_cc, D terms; cost sum r.r into red[7]
 double run_between_cost(caspar_ba* h, const double* cam);  // 1/2 sum |r|^2 at camera rows `cam`
+void launch_between_cost(caspar_ba* h, const double* cam);  // its sum r.r into red[7], no read-back
 void run_between_product(caspar_ba* h, const void* p, bool pcg_mode);  // bt_rows and pAp partials
 unsigned between_grid(const caspar_ba* h);          // workgroups of the per-camera between kernels
 int matvec_waves(int prec, bool rj);  // waves per workgroup of the fused product

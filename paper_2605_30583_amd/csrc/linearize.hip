@@ -606,16 +606,32 @@ void run_linearize(caspar_ba* h) {
     linearize_t<double>(h);
   else
     linearize_t<float>(h);
+  launch_absmax(h, h->vec.g);  // read back with the cost sums
   const DevScalars s = read_scalars(h);
   h->cost = 0.5 * (s.red[0] + (h->n_between > 0 ? s.red[7] : 0.0));
-  h->gmax = run_absmax(h, h->vec.g);
+  h->gmax = h->N > 0 ? s.red[3] : 0.0;
   h->linearized = true;
   h->bj_lambda = -1.0;
 }
 
 double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
-  const double fb = run_between_cost(h, cam);  // pose between-factors (float64)
-  if (h->n_tiles == 0) return fb;
+  launch_cost(h, cam, X, fp64);
+  return cost_of(h, read_scalars(h));
+}
+
+double cost_of(const caspar_ba* h, const DevScalars& s) {
+  return 0.5 * (s.red[1] + (h->n_between > 0 ? s.red[7] : 0.0));
+}
+
+// Reprojection cost sum into red[1] (zero without observations) and the
+// between-factor sum into red[7].
+void launch_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
+  launch_between_cost(h, cam);  // pose between-factors (float64)
+  if (h->n_tiles == 0) {
+    k_sum_partials<<<1, 1024, 0, h->stream>>>(0, h->partials, 0, h->scal, 1);
+    CBA_LAUNCHED();
+    return;
+  }
   hipStream_t st = h->stream;
   const bool f64 = fp64 || h->prec == CASPAR_FP64;
   const unsigned tg = f64 ? tile_grid<k_cost<double>>(h->n_tiles) : tile_grid<k_cost<float>>(h->n_tiles);
@@ -634,7 +650,6 @@ double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64) {
   CBA_LAUNCHED();
   k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 1);
   CBA_LAUNCHED();
-  return 0.5 * read_scalars(h).red[1] + fb;
 }
 
 template <typename S>

@@ -518,9 +518,12 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
                                                   kMaxPartials);
   const unsigned pg = (unsigned)std::min<int64_t>(nblk(std::max<int64_t>(N / 4, 1), 256), 4096);
   check_every = std::max(1, check_every);
-  DevScalars s = read_scalars(h);
+  // the first batch is enqueued without reading the start state: if the
+  // start already stopped PCG (zero right-hand side, no iterations allowed),
+  // its kernels exit at once
+  DevScalars s{};
   int launched = 0;
-  while (!s.done && launched <= max_iters) {
+  do {
     for (int k = 0; k < check_every; ++k) {
       // the first product pads the camera rows of p itself; later ones use
       // the rows written by k_pcg_p
@@ -535,7 +538,7 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
     }
     launched += check_every;
     s = read_scalars(h);
-  }
+  } while (!s.done && launched <= max_iters);
   timing_harvest(h, s.iter);
   if (!s.done) fail(CASPAR_ENUMERIC, "internal: PCG did not reach its stop condition");
   if (rel_resid) *rel_resid = s.bb > 0.0 ? std::sqrt(std::max(s.rr, 0.0) / s.bb) : 0.0;
@@ -550,9 +553,8 @@ int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double to
   return pcg_t<float>(h, lambda, (const float*)b, negate_b, tol, max_iters, check_every, rel_resid);
 }
 
-void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx) {
+void launch_pred_dots(caspar_ba* h) {
   const int64_t N = h->N;
-  *gx = *xr = *xDx = 0.0;
   if (N == 0) return;
   const unsigned g = vec_grid(N);
   if (h->prec == CASPAR_FP64)
@@ -564,10 +566,18 @@ void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx) {
   CBA_LAUNCHED();
   k_reduce_pred<<<1, 1024, 0, h->stream>>>((int)g, h->partials, h->scal);
   CBA_LAUNCHED();
-  const DevScalars sc = read_scalars(h);
-  *gx = sc.red[4];
-  *xr = sc.red[5];
-  *xDx = sc.red[6];
+}
+
+void pred_dots_of(const caspar_ba* h, const DevScalars& sc, double* gx, double* xr, double* xDx) {
+  const bool any = h->N > 0;
+  *gx = any ? sc.red[4] : 0.0;
+  *xr = any ? sc.red[5] : 0.0;
+  *xDx = any ? sc.red[6] : 0.0;
+}
+
+void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx) {
+  launch_pred_dots(h);
+  pred_dots_of(h, read_scalars(h), gx, xr, xDx);
 }
 
 double run_dot(caspar_ba* h, const void* a, const void* b, const void* e) {
@@ -584,9 +594,9 @@ double run_dot(caspar_ba* h, const void* a, const void* b, const void* e) {
   return read_scalars(h).red[2];
 }
 
-double run_absmax(caspar_ba* h, const void* a) {
+void launch_absmax(caspar_ba* h, const void* a) {
   const int64_t N = h->N;
-  if (N == 0) return 0.0;
+  if (N == 0) return;
   const unsigned g = vec_grid(N);
   if (h->prec == CASPAR_FP64)
     k_absmax<double><<<g, 256, 0, h->stream>>>(N, (const double*)a, h->partials);
@@ -595,6 +605,11 @@ double run_absmax(caspar_ba* h, const void* a) {
   CBA_LAUNCHED();
   k_reduce_partials<<<1, 1024, 0, h->stream>>>((int)g, h->partials, 1, h->scal, 3);
   CBA_LAUNCHED();
+}
+
+double run_absmax(caspar_ba* h, const void* a) {
+  if (h->N == 0) return 0.0;
+  launch_absmax(h, a);
   return read_scalars(h).red[3];
 }
 

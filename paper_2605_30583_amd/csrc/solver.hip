@@ -207,17 +207,22 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
     double rel = 0.0;
     const int k = run_pcg(h, lam, h->vec.g, true, o.pcg_tol, o.max_pcg_iters, o.pcg_check_every, nullptr, &rel);
     pcg_total += k;
-    // pred = 1/2 (-g^T x + x^T r + lambda x^T D x)
+    // pred = 1/2 (-g^T x + x^T r + lambda x^T D x); its dot products, the
+    // trial parameters and the trial cost are enqueued together and read
+    // back once
+    launch_pred_dots(h);
+    run_retract(h, h->vec.x);
+    launch_cost(h, h->cam_trial, h->X_trial, false);
+    const DevScalars sc = read_scalars(h);
     double gx, xr, xDx;
-    run_pred_dots(h, &gx, &xr, &xDx);
+    pred_dots_of(h, sc, &gx, &xr, &xDx);
     const double pred = 0.5 * (-gx + xr + lam * xDx);
     if (o.pred_tol > 0.0 && pred <= o.pred_tol * h->cost) {
       // the model predicts no decrease the cost could resolve
       reason = 3;
       break;
     }
-    run_retract(h, h->vec.x);
-    const double Ft = run_cost(h, h->cam_trial, h->X_trial, false);
+    const double Ft = cost_of(h, sc);
     const double F = h->cost;
     const double rho = (pred > 0.0 && std::isfinite(Ft)) ? (F - Ft) / pred
                                                          : -std::numeric_limits<double>::infinity();
