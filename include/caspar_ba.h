@@ -94,7 +94,9 @@ typedef struct caspar_solve_opts {
   double lambda_max;     /* default 1e16 */
   double grad_tol;       /* stop when ||g||_inf <= grad_tol * max(1, ||g_0||_inf); default 1e-12 */
   double min_cost;       /* stop when the cost F <= min_cost; default 1e-30 */
-  int32_t pcg_check_every; /* host polls PCG convergence every this many iterations; default 4 */
+  int32_t pcg_check_every; /* host polls PCG convergence every this many iterations; within a
+                              solve, the first poll of an LM step's PCG comes after
+                              max(this, the previous step's PCG iterations - this); default 4 */
   int32_t flags;         /* reserved, 0 */
   double pred_tol;       /* stop when the step's predicted decrease pred <= pred_tol * F; default 0
                             (never).  Once pred falls below the resolution of F (about 1e-16 F) the

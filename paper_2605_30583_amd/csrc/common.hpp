@@ -356,7 +356,8 @@ void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mo
 void run_block_jacobi(caspar_ba* h, double lambda);
 void run_bj_apply(caspar_ba* h, const void* r, void* z);
 int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double tol, int max_iters,
-            int check_every, void* x, double* rel_resid);
+            int check_every, void* x, double* rel_resid, int first_batch = 0);  // first poll after
+                                                                              // max(check_every, first_batch)
 double run_dot(caspar_ba* h, const void* a, const void* b, const void* wdiag);  // sum a b (w)
 void run_pred_dots(caspar_ba* h, double* gx, double* xr, double* xDx);  // g^T x, x^T r, x^T D x
 void launch_pred_dots(caspar_ba* h);                // the same into red[4..6], no read-back

@@ -497,7 +497,7 @@ void run_bj_apply(caspar_ba* h, const void* r, void* z) {
 
 template <typename S>
 static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double tol, int max_iters,
-                 int check_every, double* rel_resid) {
+                 int check_every, double* rel_resid, int first_batch) {
   hipStream_t st = h->stream;
   const int64_t nb = (int64_t)h->nc + h->np;
   const int64_t N = h->N;
@@ -520,11 +520,14 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
   check_every = std::max(1, check_every);
   // the first batch is enqueued without reading the start state: if the
   // start already stopped PCG (zero right-hand side, no iterations allowed),
-  // its kernels exit at once
+  // its kernels exit at once.  The caller may size it from an expected
+  // iteration count (successive LM steps need similar counts), so the host
+  // reads back about twice per solve instead of every check_every.
   DevScalars s{};
   int launched = 0;
+  int batch = std::max(check_every, std::min(first_batch, max_iters));
   do {
-    for (int k = 0; k < check_every; ++k) {
+    for (int k = 0; k < batch; ++k) {
       // the first product pads the camera rows of p itself; later ones use
       // the rows written by k_pcg_p
       run_matvec(h, lambda, p, w, true, launched + k == 0);
@@ -536,7 +539,8 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
                                      h->scal);
       CBA_LAUNCHED();
     }
-    launched += check_every;
+    launched += batch;
+    batch = check_every;
     s = read_scalars(h);
   } while (!s.done && launched <= max_iters);
   timing_harvest(h, s.iter);
@@ -546,11 +550,12 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
 }
 
 int run_pcg(caspar_ba* h, double lambda, const void* b, bool negate_b, double tol, int max_iters,
-            int check_every, void* x, double* rel_resid) {
+            int check_every, void* x, double* rel_resid, int first_batch) {
   (void)x;
   if (h->prec == CASPAR_FP64)
-    return pcg_t<double>(h, lambda, (const double*)b, negate_b, tol, max_iters, check_every, rel_resid);
-  return pcg_t<float>(h, lambda, (const float*)b, negate_b, tol, max_iters, check_every, rel_resid);
+    return pcg_t<double>(h, lambda, (const double*)b, negate_b, tol, max_iters, check_every, rel_resid,
+                         first_batch);
+  return pcg_t<float>(h, lambda, (const float*)b, negate_b, tol, max_iters, check_every, rel_resid, first_batch);
 }
 
 void launch_pred_dots(caspar_ba* h) {

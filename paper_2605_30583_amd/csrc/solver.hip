@@ -194,7 +194,7 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
   const double g0 = h->gmax;
   double lam = std::min(std::max(o.lambda0, o.lambda_min), o.lambda_max);
   double nu = 2.0;
-  int iters = 0, accepted = 0, pcg_total = 0, reason = 0;
+  int iters = 0, accepted = 0, pcg_total = 0, reason = 0, prev_pcg = 0;
   for (int it = 0; it < o.max_lm_iters; ++it) {
     if (h->gmax <= o.grad_tol * std::max(1.0, g0)) {
       reason = 1;
@@ -205,7 +205,10 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
       break;
     }
     double rel = 0.0;
-    const int k = run_pcg(h, lam, h->vec.g, true, o.pcg_tol, o.max_pcg_iters, o.pcg_check_every, nullptr, &rel);
+    // the previous step's PCG count sizes the first batch before a poll
+    const int k = run_pcg(h, lam, h->vec.g, true, o.pcg_tol, o.max_pcg_iters, o.pcg_check_every, nullptr, &rel,
+                          prev_pcg - o.pcg_check_every);
+    prev_pcg = k;
     pcg_total += k;
     // pred = 1/2 (-g^T x + x^T r + lambda x^T D x); its dot products, the
     // trial parameters and the trial cost are enqueued together and read

@@ -132,3 +132,36 @@ def test_removing_the_factors_restores_the_plain_problem_and_bad_input_is_refuse
     b.set_between(fi, fj, Z, w)
     with pytest.raises(CasparError, match="gauge"):
         b.backward(None, torch.zeros((sc.n_points, 3), dtype=torch.float64, device="cuda"), gauge_project=True)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 3e-6)], ids=["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
+def test_ragged_scene_with_factors_on_an_unobserved_camera(precision, tol, rj):
+    """Ragged degrees, a point split across tiles, an orphan point, and a
+    camera seen by no observation that only its between-factors tie down."""
+    from gpu_helpers import ragged_scene
+    sc = ragged_scene()
+    px = observed_pixels(sc)
+    nc = sc.n_cams
+    fi = np.array([0, 5, 79, 80, 80, 12], np.int32)
+    fj = np.array([1, 80, 3, 7, 44, 13], np.int32)
+    st_true = camera.State.from_bal(sc.cams_true, sc.points_true)
+    rng = np.random.default_rng(8)
+    Z, w = between.measurements(st_true, fi, fj, rng.normal(size=(6, 3)), rng.normal(size=(6, 3)), 3e-3, 2e-2)
+    assert nc == 81 and not np.any(sc.obs_cam == 80)
+    bf = (fi, fj, Z, w)
+    ba = handle_for(sc, px, precision, rj=rj)
+    ba.set_between(*bf)
+    out = ba.linearize()
+    st, F, J, g, D = _oracle_system(sc, px, bf)
+    assert abs(out["cost"] - F) <= tol * F
+    assert rel(out["grad"].cpu(), g) <= 10 * tol
+    assert rel(out["diag"].cpu(), D) <= 10 * tol
+    p = rng.normal(size=st.n_params)
+    lam = 1e-2
+    wv, pap = ba.matvec(lam, t64(p))
+    ref = linear.matvec(J, D, lam, p)
+    assert rel(wv.cpu(), ref) <= 10 * tol
+    assert abs(pap - p @ ref) <= 10 * tol * abs(p @ ref)
+    cam80 = slice(9 * 80, 9 * 81)
+    assert rel(wv.cpu()[cam80], ref[cam80]) <= 10 * tol        # the camera the factors alone hold
