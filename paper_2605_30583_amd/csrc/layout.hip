@@ -157,13 +157,31 @@ __global__ void k_validate(int nc, int np, int no, const double* __restrict__ ca
   if (err) atomicOr(&sc->err, err);
 }
 
+// Observation counts per point (global atomics: a point has few
+// observations, so they rarely collide) and, without the LDS histogram
+// below, per camera too.
 __global__ void k_count(int no, const int* __restrict__ oc, const int* __restrict__ op,
                         int* cam_cnt, int* pt_cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < no) {
-    atomicAdd(&cam_cnt[oc[i]], 1);
+    if (cam_cnt != nullptr) atomicAdd(&cam_cnt[oc[i]], 1);
     atomicAdd(&pt_cnt[op[i]], 1);
   }
+}
+
+// Observation counts per camera through a per-workgroup LDS histogram: the
+// most observed cameras take millions of increments, which global atomics
+// serialise at one address; each workgroup adds its bins once at the end.
+constexpr int kCountLdsCams = 32768;  // 128 KiB of LDS
+__global__ __launch_bounds__(1024) void k_count_cams(int no, const int* __restrict__ oc, int nc, int* cam_cnt) {
+  extern __shared__ int hist[];
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < no; o += gridDim.x * blockDim.x)
+    atomicAdd(&hist[oc[o]], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nc; i += blockDim.x)
+    if (hist[i] != 0) atomicAdd(&cam_cnt[i], hist[i]);
 }
 
 __global__ void k_point_key(int no, const int* __restrict__ oc, const int* __restrict__ op,
@@ -409,7 +427,15 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   if (nc) CBA_HIP(hipMemsetAsync(cam_cnt, 0, 4 * (size_t)nc, st));
   if (np) CBA_HIP(hipMemsetAsync(pt_cnt, 0, 4 * (size_t)np, st));
   if (no) {
-    k_count<<<blocks_for(no, 256), 256, 0, st>>>(no, oc, op, cam_cnt, pt_cnt);
+    const bool lds_hist = nc <= kCountLdsCams;
+    if (lds_hist) {
+      const size_t lds = (size_t)nc * sizeof(int);
+      if (lds > 65536)
+        CBA_HIP(hipFuncSetAttribute((const void*)k_count_cams, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      k_count_cams<<<std::min<unsigned>(blocks_for(no, 1024), kNumCUs), 1024, lds, st>>>(no, oc, nc, cam_cnt);
+      CBA_LAUNCHED();
+    }
+    k_count<<<blocks_for(no, 256), 256, 0, st>>>(no, oc, op, lds_hist ? nullptr : cam_cnt, pt_cnt);
     CBA_LAUNCHED();
   }
   std::vector<int> ccnt = d2h(h, cam_cnt, nc);
