@@ -345,30 +345,39 @@ __global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chun
 }
 
 // Per camera (one workgroup): sum the chunk rows into g_c, H_cc and D_c.
-// Lane k of each wave takes value k (k < 54) of every fourth chunk, so each
-// wave reads whole 432-byte rows; the four wave sums are added in LDS.
+// Lane k of each of the 16 waves takes value k (k < 54) of every 16th chunk
+// with four independent accumulators, so each wave reads whole 432-byte
+// rows and the most observed camera (over a thousand chunks) keeps 64 rows
+// in flight; the 16 wave sums are added in LDS.
+constexpr int kCamFinalWaves = 16;
+
 template <typename S>
-__global__ __launch_bounds__(256) void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
-                                                       const double* __restrict__ rows, S* g, S* D,
-                                                       double* Hcc) {
-  __shared__ double red[4][kCamRowWidth];
+__global__ __launch_bounds__(kCamFinalWaves * 64) void k_lin_cam_final(int nc, const int* __restrict__ chunk_off,
+                                                                        const double* __restrict__ rows, S* g, S* D,
+                                                                        double* Hcc) {
+  constexpr int W = kCamFinalWaves;
+  __shared__ double red[W][kCamRowWidth];
   const int c = blockIdx.x;
   const int k = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int q0 = chunk_off[c], q1 = chunk_off[c + 1];
   if (k < kCamRowWidth) {
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int q = q0 + wv;
-    for (; q + 4 < q1; q += 8) {
+    for (; q + 3 * W < q1; q += 4 * W) {
       s0 += rows[(size_t)q * kCamRowWidth + k];
-      s1 += rows[(size_t)(q + 4) * kCamRowWidth + k];
+      s1 += rows[(size_t)(q + W) * kCamRowWidth + k];
+      s2 += rows[(size_t)(q + 2 * W) * kCamRowWidth + k];
+      s3 += rows[(size_t)(q + 3 * W) * kCamRowWidth + k];
     }
-    if (q < q1) s0 += rows[(size_t)q * kCamRowWidth + k];
-    red[wv][k] = s0 + s1;
+    for (; q < q1; q += W) s0 += rows[(size_t)q * kCamRowWidth + k];
+    red[wv][k] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   if (threadIdx.x < kCamRowWidth) {
     const int t = threadIdx.x;
-    const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) s += red[i][t];
     if (t < 9) {
       g[9 * (size_t)c + t] = (S)s;
     } else {
@@ -595,7 +604,7 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->nc > 0) {
-    k_lin_cam_final<S><<<h->nc, 256, 0, st>>>(h->nc, h->chunk_off, h->chunk_rows, g, D, h->Hcc);
+    k_lin_cam_final<S><<<h->nc, kCamFinalWaves * 64, 0, st>>>(h->nc, h->chunk_off, h->chunk_rows, g, D, h->Hcc);
     CBA_LAUNCHED();
   }
   run_between_lin(h);  // pose between-factors: their g, H_cc, D terms and cost
