@@ -100,6 +100,26 @@ def counter_traffic(workload: str, precision: str, jacobian: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def measure_copy(torch, dev, mib: int = 1024, reps: int = 10):
+    """Rate of a plain device-to-device copy (read + write bytes), the
+    practical HBM ceiling the bandwidth-bound kernels are compared with."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"what": f"device-to-device copy of a {mib} MiB float32 tensor, {reps} repetitions, "
+                    "read plus written bytes over HIP event time", "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
 def cpu_baseline(sc, n_points: int, pcg_tol: float):
     """The oracle (float64, NumPy/SciPy, unchanged) on a bounded sample: the
     first n_points points with all their observations, one LM iteration with
@@ -168,6 +188,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {n} bytes read, {n} bytes written")
         del src, dst
+    copy = measure_copy(torch, dev)
+    log(f"device copy: {copy['gbs']:.0f} GB/s")
     t = time.time()
     sc = scene_config(a.workload)
     log(f"scene {a.workload}: {sc.n_cams} cameras, {sc.n_points} points, {sc.n_obs} observations "
@@ -247,6 +269,7 @@ def main():
             "matvec_algorithmic_bytes": tim_alt["matvec_bytes"],
             "matvec_gbs": gbs_alt,
             "matvec_hbm_frac": gbs_alt / HBM_PEAK_GBS,
+            "matvec_frac_of_copy": gbs_alt / copy["gbs"],
             "matvec_tflops": FLOPS_PER_OBS[alt] * sc.n_obs / (mv_alt * 1e-3) / 1e12,
         }
         del ba_alt
@@ -332,6 +355,7 @@ def main():
         },
         "roofline": roofline,
     }
+    line["hbm_copy"] = copy
     line.update(extra)
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")

@@ -77,3 +77,62 @@ def test_large_workload_cost_gradient_and_product(large, precision, tol, rj):
     assert rel(d, d_ref) <= tol
     assert rel(w, w_ref) <= tol
     ba.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-5)])
+def test_large_workload_with_between_factors(large, precision, tol):
+    """The same workload plus pose between-factors (a camera chain and
+    n_cams/8 loop closures, 15,411 factors), recomputed blocks: the total cost
+    against the oracle's reprojection and factor costs over everything, and
+    the gradient, damping diagonal and product at the sampled columns, the
+    factor rows taken in full."""
+    from oracle import between
+    from helpers import between_factors
+    import scipy.sparse as sp
+    sc, px, st0, cost, cams, pts = large
+    fi, fj, Z, wts = between_factors(sc, seed=7, n_loops=sc.n_cams // 8)
+    ba = handle_for(sc, px, precision, rj=True)
+    ba.set_between(fi, fj, Z, wts)
+    lin = ba.linearize()
+    rb, Ji, Jj = between.linearize(st0, fi, fj, Z, wts)
+    cost_b = 0.5 * float(np.sum(rb * rb))
+    assert abs(lin["cost"] - (cost + cost_b)) <= tol * (cost + cost_b)
+    lam = 1e-2
+    p = np.random.default_rng(3).normal(size=9 * sc.n_cams + 3 * sc.n_points)
+    w, _ = ba.matvec(lam, t64(p))
+    rows = np.isin(sc.obs_cam, cams) | np.isin(sc.obs_pt, pts)
+    oc, op = sc.obs_cam[rows], sc.obs_pt[rows]
+    r, Jc, Jp = camera.linearize(st0, oc, op, px[rows])
+    J = sp.vstack([linear.jacobian_csr(Jc, Jp, oc, op, sc.n_cams, sc.n_points),
+                   between.jacobian_csr(Ji, Jj, fi, fj, sc.n_cams, sc.n_points)]).tocsr()
+    rr = np.concatenate([r.ravel(), rb.ravel()])
+    D = linear.damping_diagonal(J)
+    cols = np.concatenate([(9 * cams[:, None] + np.arange(9)).ravel(),
+                           (9 * sc.n_cams + 3 * pts[:, None] + np.arange(3)).ravel()])
+    assert rel(lin["grad"].cpu().numpy()[cols], linear.gradient(J, rr)[cols]) <= tol
+    assert rel(lin["diag"].cpu().numpy()[cols], D[cols]) <= tol
+    assert rel(w.cpu().numpy()[cols], linear.matvec(J, D, lam, p)[cols]) <= tol
+    ba.close()
+
+
+def test_large_workload_pcg_residual(large):
+    """The solve's inner step at full size, as the benchmark runs it
+    (float32-mixed, recomputed blocks, tolerance 1e-3): the float64 residual
+    of the returned step, b - (J^T J + lambda D) x with the float64 product
+    (checked against the oracle above), is within the tolerance; so is the
+    float64 path's own step."""
+    sc, px, st0, cost, cams, pts = large
+    lam, tol = 1e-2, 1e-3
+    ba64 = handle_for(sc, px, 0, rj=True)
+    b = -ba64.linearize()["grad"]
+    nb = float(b.norm())
+    ba32 = handle_for(sc, px, 1, rj=True)
+    for name, ba, slack in (("float32-mixed", ba32, 1.05), ("float64", ba64, 1.001)):
+        x, iters, rel_res = ba.pcg(lam, b, tol, 500)
+        ax, _ = ba64.matvec(lam, x)
+        true_rel = float((b - ax).norm()) / nb
+        print(f"{name}: {iters} iterations, recurrence {rel_res:.6e}, float64 residual {true_rel:.6e}", flush=True)
+        assert 0 < iters < 500 and rel_res <= tol
+        assert true_rel <= slack * tol
+    ba32.close()
+    ba64.close()
