@@ -19,6 +19,31 @@ __host__ __device__ constexpr int tri_idx(int n, int k, int l) {
   return k * n - k * (k - 1) / 2 + (l - k);
 }
 
+// Cholesky factor L of A + jitter I (lower triangle).  Every loop has a
+// fixed trip count, so the matrices stay in registers; a non-positive or
+// non-finite pivot makes the result false (the factor is then garbage and
+// is not used).
+template <int n>
+__device__ inline bool cholesky(const double (&A)[n][n], double jitter, double (&L)[n][n]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    double s = A[j][j] + jitter;
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+    ok = ok & (s > 0.0) & (bool)isfinite(s);
+    L[j][j] = sqrt(s);
+#pragma unroll
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+      L[i][j] = t / L[j][j];
+    }
+  }
+  return ok;
+}
+
 // Inverse of the n x n symmetric positive definite matrix given by its packed
 // upper triangle plus lambda * diag(d); result packed the same way.
 // Cholesky A = L L^T, W = L^-1, A^-1 = W^T W.  On a non-positive pivot the
@@ -38,25 +63,8 @@ __device__ void spd_inverse(const double* __restrict__ Hup, const double* dg, do
       A[l][k] = v;
       if (k == l) tr += v;
     }
-  bool ok = false;
-  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
-    const double jitter = attempt == 0 ? 0.0 : 1e-12 * fabs(tr);
-    ok = true;
-    for (int j = 0; j < n && ok; ++j) {
-      double s = A[j][j] + jitter;
-      for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-      if (!(s > 0.0) || !isfinite(s)) {
-        ok = false;
-        break;
-      }
-      L[j][j] = sqrt(s);
-      for (int i = j + 1; i < n; ++i) {
-        double t = A[i][j];
-        for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-        L[i][j] = t / L[j][j];
-      }
-    }
-  }
+  bool ok = cholesky<n>(A, 0.0, L);
+  if (!ok) ok = cholesky<n>(A, 1e-12 * fabs(tr), L);
   if (!ok) {
 #pragma unroll
     for (int k = 0; k < n; ++k)
@@ -64,41 +72,51 @@ __device__ void spd_inverse(const double* __restrict__ Hup, const double* dg, do
       for (int l = k; l < n; ++l) out[tri_idx(n, k, l)] = (k == l && A[k][k] > 0.0) ? 1.0 / A[k][k] : 0.0;
     return;
   }
+#pragma unroll
   for (int j = 0; j < n; ++j) {
     W[j][j] = 1.0 / L[j][j];
+#pragma unroll
     for (int i = j + 1; i < n; ++i) {
       double s = 0.0;
+#pragma unroll
       for (int k = j; k < i; ++k) s += L[i][k] * W[k][j];
       W[i][j] = -s / L[i][i];
     }
   }
+#pragma unroll
   for (int a = 0; a < n; ++a)
+#pragma unroll
     for (int b = a; b < n; ++b) {
       double s = 0.0;
+#pragma unroll
       for (int m = b; m < n; ++m) s += W[m][a] * W[m][b];
       out[tri_idx(n, a, b)] = s;
     }
 }
 
 template <typename S>
-__global__ void k_bj_cams(int nc, const double* __restrict__ Hcc, const S* __restrict__ D, double lambda,
-                          S* __restrict__ Mc) {
+__global__ __launch_bounds__(256) void k_bj_cams(int nc, const double* __restrict__ Hcc, const S* __restrict__ D,
+                                                 double lambda, S* __restrict__ Mc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   double dg[9], inv[45];
+#pragma unroll
   for (int k = 0; k < 9; ++k) dg[k] = (double)D[9 * (size_t)c + k];
   spd_inverse<9>(Hcc + 45 * (size_t)c, dg, lambda, inv);
+#pragma unroll
   for (int k = 0; k < 45; ++k) Mc[45 * (size_t)c + k] = (S)inv[k];
 }
 
 template <typename S>
-__global__ void k_bj_points(int np, const double* __restrict__ Hpp, const S* __restrict__ Dp, double lambda,
-                            S* __restrict__ Mp) {
+__global__ __launch_bounds__(256) void k_bj_points(int np, const double* __restrict__ Hpp, const S* __restrict__ Dp,
+                                                   double lambda, S* __restrict__ Mp) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   double dg[3], inv[6];
+#pragma unroll
   for (int k = 0; k < 3; ++k) dg[k] = (double)Dp[3 * (size_t)i + k];
   spd_inverse<3>(Hpp + 6 * (size_t)i, dg, lambda, inv);
+#pragma unroll
   for (int k = 0; k < 6; ++k) Mp[6 * (size_t)i + k] = (S)inv[k];
 }
 
