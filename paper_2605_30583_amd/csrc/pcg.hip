@@ -152,6 +152,25 @@ __global__ void k_bj_apply(int nc, int np, const S* __restrict__ Mc, const S* __
   }
 }
 
+// One block of the start: x = 0, r = +-b, z = M^-1 r, p = z, held in
+// registers between the reads and the writes.
+template <typename S, int n>
+__device__ inline void init_block(const S* __restrict__ Minv, const S* __restrict__ b, double sign, size_t o,
+                                  S* __restrict__ x, S* __restrict__ r, S* __restrict__ z, S* __restrict__ p,
+                                  double& rz, double& rr) {
+  S rv[n], zv[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) rv[k] = (S)(sign * (double)b[o + k]);
+  block_apply<S, n>(Minv, rv, zv, rz, rr);
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    r[o + k] = rv[k];
+    x[o + k] = (S)0;
+    z[o + k] = zv[k];
+    p[o + k] = zv[k];
+  }
+}
+
 // x = 0, r = +-b, z = M^-1 r, p = z; partials: r^T z, r^T r.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_init(int nc, int np, const S* __restrict__ Mc,
@@ -164,18 +183,10 @@ __global__ __launch_bounds__(256) void k_pcg_init(int nc, int np, const S* __res
   const int64_t nb = (int64_t)nc + np;
   for (int64_t blk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; blk < nb;
        blk += (int64_t)gridDim.x * blockDim.x) {
-    const bool cam = blk < nc;
-    const int n = cam ? 9 : 3;
-    const size_t o = cam ? 9 * (size_t)blk : 9 * (size_t)nc + 3 * (size_t)(blk - nc);
-    for (int k = 0; k < n; ++k) {
-      r[o + k] = (S)(sign * (double)b[o + k]);
-      x[o + k] = (S)0;
-    }
-    if (cam)
-      block_apply<S, 9>(Mc + 45 * blk, r + o, z + o, rz, rr);
+    if (blk < nc)
+      init_block<S, 9>(Mc + 45 * blk, b, sign, 9 * (size_t)blk, x, r, z, p, rz, rr);
     else
-      block_apply<S, 3>(Mp + 6 * (blk - nc), r + o, z + o, rz, rr);
-    for (int k = 0; k < n; ++k) p[o + k] = z[o + k];
+      init_block<S, 3>(Mp + 6 * (blk - nc), b, sign, 9 * (size_t)nc + 3 * (size_t)(blk - nc), x, r, z, p, rz, rr);
   }
   const double a = block_sum(rz, red);
   const double c = block_sum(rr, red);
