@@ -141,7 +141,9 @@ CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, in
  * cams (dev) [n_cams][9] BAL; points (dev) [n_points][3]; obs_cam, obs_pt
  * (dev) int32 [n_obs]; obs_px (dev) [n_obs][2].  workspace (dev, >= 256-byte
  * aligned, caspar_ba_workspace_bytes() long) must outlive the handle; the
- * library never allocates device memory of its own.  Inputs are validated
+ * library never allocates device memory of its own (the handle keeps one
+ * small pinned host buffer for reading back solver scalars, freed by
+ * caspar_ba_destroy).  Inputs are validated
  * (indices in range, values finite -> CASPAR_EINVAL).  The observations are
  * reordered internally (point-major, points grouped by their least-observed
  * camera); that order never shows at the boundary. */

@@ -252,6 +252,7 @@ struct caspar_ba {
   double* partials = nullptr;   // [kMaxPartials][4]
   double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
   cba::DevScalars* scal = nullptr;
+  cba::DevScalars* scal_host = nullptr;  // pinned host memory the scalar read-backs land in
 
   // kernel timing (roofline reporting)
   bool timing = false;

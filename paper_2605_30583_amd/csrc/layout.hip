@@ -349,11 +349,12 @@ static void cast_pixels(caspar_ba* h) {
 
 void sync(caspar_ba* h) { CBA_HIP(hipStreamSynchronize(h->stream)); }
 
+// A copy into pinned memory goes straight to the host; into pageable memory
+// it would be staged through a runtime buffer, a longer round trip.
 DevScalars read_scalars(caspar_ba* h) {
-  DevScalars s;
-  CBA_HIP(hipMemcpyAsync(&s, h->scal, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+  CBA_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
   sync(h);
-  return s;
+  return *h->scal_host;
 }
 
 void upload_cameras_bal(caspar_ba* h, const double* bal, double* cam) {
@@ -654,6 +655,7 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
 }  // namespace cba
 
 caspar_ba::~caspar_ba() {
+  if (scal_host) (void)hipHostFree(scal_host);
   for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
 }
@@ -730,6 +732,7 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
     CBA_HIP(hipGetDevice(&h->device));
     char* ws = (char*)workspace;
     h->scal = (DevScalars*)(ws + plan.scal.off);
+    CBA_HIP(hipHostMalloc((void**)&h->scal_host, sizeof(DevScalars), hipHostMallocDefault));
     h->partials = (double*)(ws + plan.partials.off);
     h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
     h->cam = (double*)(ws + plan.cam.off);

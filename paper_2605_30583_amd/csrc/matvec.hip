@@ -585,9 +585,10 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
 void timing_mark_start(caspar_ba* h) {
   if (!h->timing) return;
   if (h->ev_used == (int)h->ev_start.size()) {
+    // timing only: no system-scope fence (cache write-back) at each record
     hipEvent_t a, b;
-    CBA_HIP(hipEventCreate(&a));
-    CBA_HIP(hipEventCreate(&b));
+    CBA_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    CBA_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     h->ev_start.push_back(a);
     h->ev_stop.push_back(b);
   }
