@@ -139,6 +139,19 @@ def cpu_baseline(sc, n_points: int, pcg_tol: float):
     lm.solve(st, oc, op, px, lm.LMOptions(max_iters=1, inner="pcg", pcg_tol=pcg_tol))
     dt = time.perf_counter() - t
     frac = float(m.sum()) / sc.n_obs
+    # the oracle's sparse product (J^T (J p) + lambda D p) on the same sample,
+    # priced on the bytes the method must move (float64 B_mv)
+    from oracle import linear
+    _, Jc, Jp = camera.linearize(st, oc, op, px)
+    J = linear.jacobian_csr(Jc, Jp, oc, op, sc.n_cams, n_points)
+    D = linear.damping_diagonal(J)
+    p = np.random.default_rng(0).normal(size=J.shape[1])
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        linear.matvec(J, D, 1e-2, p)
+        times.append(time.perf_counter() - t)
+    b_mv = float(m.sum()) * (24 * 8 + 8) + 3 * 8 * J.shape[1]
     return {
         "value": frac / dt,
         "unit": "LM iterations/s",
@@ -147,6 +160,8 @@ def cpu_baseline(sc, n_points: int, pcg_tol: float):
         "sample": (f"1 LM iteration (PCG inner, tol {pcg_tol:g}) on the first {n_points} points and their "
                    f"{int(m.sum())} observations ({100 * frac:.2f}% of the workload) in {dt:.1f} s; rate scaled "
                    f"by the observation fraction; sparse products run on one thread, BLAS on {blas}"),
+        "matvec_gbs": b_mv / float(np.median(times)) / 1e9,
+        "matvec_sample": "the oracle's sparse product on the same sample, float64 B_mv bytes over the median of 3 runs",
     }
 
 
