@@ -368,8 +368,7 @@ void launch_absmax(caspar_ba* h, const void* a);    // max |a| into red[3], no r
 void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
 void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);
 void run_zero(caspar_ba* h, void* v, size_t count_scalars);
-void timing_mark_start(caspar_ba* h);
-void timing_mark_stop(caspar_ba* h);
+void timing_events(caspar_ba* h, hipEvent_t* start, hipEvent_t* stop);  // null pair when timing is off
 void timing_harvest(caspar_ba* h, int effective);  // after a sync: count the first `effective` launches
 double matvec_algorithmic_bytes(const caspar_ba* h);
 // between.hip

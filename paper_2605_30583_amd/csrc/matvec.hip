@@ -19,6 +19,10 @@
 // A second small kernel adds the per-workgroup rows and cold rows of each
 // camera (fixed order: deterministic), handles split and orphan points and
 // turns the p^T A p partials into alpha for PCG.
+#include <hip/hip_ext.h>
+
+#include <mutex>
+
 #include "common.hpp"
 #include "model.hpp"
 
@@ -535,18 +539,30 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = matvec_lds_bytes(h->K, h->L);
   auto kern = k_matvec<S, RJ>;
-  if (lds > 65536)
-    CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  timing_mark_start(h);
-  kern<<<h->G, T, lds, h->stream>>>(h->n_tiles, h->G, h->tiles, h->meta, h->J, (const S*)pts_table(h),
-                                     (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D, lambda, w, h->nc,
-                                     h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows, h->win_rows,
-                                     h->split_rows, h->partials, scp, P, h->L, h->cold_local_base,
-                                     (unsigned)(3 * (size_t)h->np * sizeof(S)),
-                                     (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)),
-                                     RJ ? weights_of<S>(h) : nullptr);
+  // the dynamic-LDS limit belongs to the kernel on a device: raised only when
+  // a launch needs more than it was last set to (not at every launch)
+  {
+    static std::mutex mu;
+    static std::vector<size_t> lds_set;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)h->device >= lds_set.size()) lds_set.resize((size_t)h->device + 1, 65536);
+    if (lds > lds_set[h->device]) {
+      CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      lds_set[h->device] = lds;
+    }
+  }
+  // with timing on, the launch itself stamps the events (no extra packets
+  // between the kernels)
+  hipEvent_t e0, e1;
+  timing_events(h, &e0, &e1);
+  hipExtLaunchKernelGGL(kern, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u, h->n_tiles, h->G, h->tiles,
+                        h->meta, h->J, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p,
+                        (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows,
+                        (S*)h->cold_rows, h->win_rows, h->split_rows, h->partials, scp, P, h->L,
+                        h->cold_local_base, (unsigned)(3 * (size_t)h->np * sizeof(S)),
+                        (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)),
+                        RJ ? weights_of<S>(h) : static_cast<const S*>(nullptr));
   CBA_LAUNCHED();
-  timing_mark_stop(h);
 }
 
 template <typename S>
@@ -581,23 +597,19 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   CBA_LAUNCHED();
 }
 
-// HIP events around each launch of the fused product (when enabled).
-void timing_mark_start(caspar_ba* h) {
+// The pair of HIP events that times the next launch of the fused product.
+void timing_events(caspar_ba* h, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
   if (!h->timing) return;
   if (h->ev_used == (int)h->ev_start.size()) {
-    // timing only: no system-scope fence (cache write-back) at each record
     hipEvent_t a, b;
-    CBA_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
-    CBA_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
+    CBA_HIP(hipEventCreate(&a));
+    CBA_HIP(hipEventCreate(&b));
     h->ev_start.push_back(a);
     h->ev_stop.push_back(b);
   }
-  CBA_HIP(hipEventRecord(h->ev_start[h->ev_used], h->stream));
-}
-
-void timing_mark_stop(caspar_ba* h) {
-  if (!h->timing) return;
-  CBA_HIP(hipEventRecord(h->ev_stop[h->ev_used], h->stream));
+  *start = h->ev_start[h->ev_used];
+  *stop = h->ev_stop[h->ev_used];
   ++h->ev_used;
 }
 
