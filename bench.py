@@ -72,6 +72,9 @@ def parse():
                     help="skip the solve with pose between-factors (camera chain plus loop closures)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-points", type=int, default=150_000)
+    ap.add_argument("--time-every", type=int, default=4,
+                    help="HIP events around every k-th launch of the fused product (each pair idles the GPU a "
+                         "few microseconds)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -234,7 +237,7 @@ def main():
             ba.solve(SolveOptions(max_lm_iters=a.warmup, pcg_tol=a.pcg_tol))
             ba.set_params(cams0, pts0)
         opts = SolveOptions(max_lm_iters=a.steps, pcg_tol=a.pcg_tol, grad_tol=0.0, min_cost=0.0)
-        ba.set_timing(True)
+        ba.set_timing(True, every=a.time_every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = ba.solve(opts, history=True)
@@ -342,6 +345,7 @@ def main():
         "kernel": "k_matvec",
         "avg_ms": mv_avg_ms,
         "launches": tim["matvec_launches"],
+        "timed_every": a.time_every,
         "algorithmic_bytes_per_launch": tim["matvec_bytes"],
         "algorithmic_flops_per_launch": FLOPS_PER_OBS[a.jacobian] * sc.n_obs,
         "hbm_gbs": gbs,

@@ -245,12 +245,13 @@ CASPAR_API int caspar_project(int32_t n_cams, int32_t n_points, int64_t n_obs, c
 CASPAR_API int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* cold_obs, int64_t* n_tiles,
                           int32_t* matvec_groups);
 
-/* Kernel timing for roofline reporting.  While enabled, every launch of the
- * fused normal-equation product made by solve/pcg/backward/matvec is
- * bracketed by HIP events on the handle's stream; launches that found the
- * PCG already finished (no work) are not counted. */
+/* Kernel timing for roofline reporting.  While enabled, every k-th launch of
+ * the fused normal-equation product made by solve/pcg/backward/matvec
+ * (counted across solves, so every position inside a solve is sampled) is
+ * timed by HIP events on the handle's stream that the launch itself stamps;
+ * launches that found the PCG already finished (no work) are not counted. */
 typedef struct caspar_timing {
-  int64_t matvec_launches;  /* fused-product launches that did work */
+  int64_t matvec_launches;  /* timed fused-product launches that did work */
   double matvec_ms;         /* summed duration of those launches (event time) */
   double matvec_bytes;      /* bytes one launch must move: per observation the
                                24 Jacobian scalars (stored mode) and two int32
@@ -259,7 +260,11 @@ typedef struct caspar_timing {
                                float64 points instead of the blocks */
 } caspar_timing;
 
-/* enable != 0 starts (and zeroes) the counters; 0 stops them. */
+/* enable = k > 0 starts (and zeroes) the counters and times every k-th
+ * launch of the fused product from here on (k = 1: every launch; the events
+ * themselves leave the GPU idle for a few microseconds per launch, so a
+ * larger k disturbs a timed solve less); 0 stops them; k < 0 is
+ * CASPAR_EINVAL.  matvec_launches then counts the timed launches. */
 CASPAR_API int caspar_ba_set_timing(caspar_ba* h, int enable);
 CASPAR_API int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out);
 

@@ -236,8 +236,10 @@ class BundleAdjuster:
         self.last_backward_iters = it.value
         return out
 
-    def set_timing(self, enable: bool):
-        check(self._lib.caspar_ba_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable: bool, every: int = 1):
+        """Event timing of the fused product (caspar_ba_set_timing): every
+        `every`-th launch while enabled."""
+        check(self._lib.caspar_ba_set_timing(self._h, int(every) if enable else 0))
 
     def get_timing(self):
         t = _native.Timing()

@@ -254,9 +254,14 @@ struct caspar_ba {
   cba::DevScalars* scal = nullptr;
   cba::DevScalars* scal_host = nullptr;  // pinned host memory the scalar read-backs land in
 
-  // kernel timing (roofline reporting)
-  bool timing = false;
+  // kernel timing (roofline reporting): every timing_every-th launch of the
+  // fused product (counted over the launches since timing was switched on)
+  // gets a pair of events; 0 is off
+  int timing_every = 0;
+  int64_t mv_seq = 0;           // product launches since timing was switched on
+  int mv_in_solve = 0;          // product launches since the last harvest
   std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<int> ev_pos;      // mv_in_solve of each timed launch
   int ev_used = 0;
   int64_t mv_launches = 0;
   double mv_ms = 0.0;
@@ -369,7 +374,7 @@ void run_to_caller_vector(caspar_ba* h, const void* internal, double* caller);
 void run_from_caller_vector(caspar_ba* h, const double* caller, void* internal);
 void run_zero(caspar_ba* h, void* v, size_t count_scalars);
 void timing_events(caspar_ba* h, hipEvent_t* start, hipEvent_t* stop);  // null pair when timing is off
-void timing_harvest(caspar_ba* h, int effective);  // after a sync: count the first `effective` launches
+void timing_harvest(caspar_ba* h, int effective);  // after a sync: count timed launches among the first `effective`
 double matvec_algorithmic_bytes(const caspar_ba* h);
 // between.hip
 void run_between_lin(caspar_ba* h);                 // adds g, H_cc, D terms; cost sum r.r into red[7]

@@ -600,30 +600,35 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
 // The pair of HIP events that times the next launch of the fused product.
 void timing_events(caspar_ba* h, hipEvent_t* start, hipEvent_t* stop) {
   *start = *stop = nullptr;
-  if (!h->timing) return;
+  if (h->timing_every <= 0) return;
+  const int pos = h->mv_in_solve++;
+  if (h->mv_seq++ % h->timing_every != 0) return;
   if (h->ev_used == (int)h->ev_start.size()) {
     hipEvent_t a, b;
     CBA_HIP(hipEventCreate(&a));
     CBA_HIP(hipEventCreate(&b));
     h->ev_start.push_back(a);
     h->ev_stop.push_back(b);
+    h->ev_pos.push_back(0);
   }
+  h->ev_pos[h->ev_used] = pos;
   *start = h->ev_start[h->ev_used];
   *stop = h->ev_stop[h->ev_used];
   ++h->ev_used;
 }
 
 void timing_harvest(caspar_ba* h, int effective) {
-  if (!h->timing) return;
-  const int n = std::min(effective, h->ev_used);
-  for (int i = 0; i < n; ++i) {
+  if (h->timing_every <= 0) return;
+  for (int i = 0; i < h->ev_used; ++i) {
+    if (h->ev_pos[i] >= effective) continue;  // the launch found the solve finished
     float ms = 0.f;
     CBA_HIP(hipEventSynchronize(h->ev_stop[i]));
     CBA_HIP(hipEventElapsedTime(&ms, h->ev_start[i], h->ev_stop[i]));
     h->mv_ms += ms;
+    ++h->mv_launches;
   }
-  h->mv_launches += n;
   h->ev_used = 0;
+  h->mv_in_solve = 0;
 }
 
 void run_matvec(caspar_ba* h, double lambda, const void* p, void* w, bool pcg_mode, bool pad_cams) {

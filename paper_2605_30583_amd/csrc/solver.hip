@@ -475,9 +475,12 @@ int caspar_ba_cost_fp64(caspar_ba* h, double* cost) {
 int caspar_ba_set_timing(caspar_ba* h, int enable) {
   CBA_API_BEGIN
   CBA_REQUIRE(h != nullptr, "handle is NULL");
-  h->timing = enable != 0;
+  CBA_REQUIRE(enable >= 0, "negative timing stride");
+  h->timing_every = enable;
   h->ev_used = 0;
-  if (h->timing) {
+  h->mv_seq = 0;
+  h->mv_in_solve = 0;
+  if (enable > 0) {
     h->mv_launches = 0;
     h->mv_ms = 0.0;
   }

@@ -90,3 +90,27 @@ def test_pose_graph_without_points(precision):
     cams, _ = ba.get_params()
     stg = camera.State.from_bal(cams.cpu().numpy(), np.zeros((0, 3)))
     assert abs(between.cost(stg, fi, fj, Z, w) - st["final_cost"]) <= 1e-10 * st["final_cost"]
+
+
+def test_product_timing_every_kth_launch(tiny):
+    """Event timing of the fused product: with stride 1 every launch that did
+    work is timed (one per PCG iteration); with stride 3 about a third of
+    them; a negative stride is refused."""
+    from paper_2605_30583_amd import SolveOptions
+    sc, px, ref = tiny
+    ba = handle_for(sc, px, rj=True)
+    counts = {}
+    for every in (1, 3):
+        ba.set_params(t64(sc.cams_init), t64(sc.points_init))
+        ba.set_timing(True, every=every)
+        st = ba.solve(SolveOptions(max_lm_iters=5, pcg_tol=1e-6))
+        tim = ba.get_timing()
+        ba.set_timing(False)
+        assert tim["matvec_ms"] > 0.0
+        counts[every] = (tim["matvec_launches"], st["pcg_iters_total"], st["lm_iters"])
+    n1, total1, _ = counts[1]
+    assert n1 == total1
+    n3, total3, lm3 = counts[3]
+    assert abs(n3 - total3 / 3.0) <= lm3 + 1, counts
+    with pytest.raises(Exception):
+        ba.set_timing(True, every=-2)
