@@ -127,3 +127,39 @@ def test_trivial_loss_is_the_plain_problem_and_bad_losses_are_rejected():
     with pytest.raises(ValueError):
         b.set_loss("tukey", 1.0)
     assert b._lib.caspar_ba_set_loss(b._h, 7, 1.0) != 0     # unknown kind: an error status
+
+
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
+def test_huber_loss_with_between_factors(scene, rj):
+    """Both widening rows at once: the Huber loss on the reprojection factors
+    beside pose between-factors (which it leaves unweighted).  Linearisation
+    and products against the oracle's stacked system; after a short solve the
+    reported cost is the oracle's objective at the returned parameters."""
+    from oracle import lm
+    from helpers import between_factors
+    from paper_2605_30583_amd import SolveOptions
+    sc, px = scene
+    bf = between_factors(sc, seed=21, n_loops=4)
+    ba = handle_for(sc, px, 0, rj=rj)
+    ba.set_loss("huber", SCALE)
+    ba.set_between(*bf)
+    out = ba.linearize()
+    st = camera.State.from_bal(sc.cams_init, sc.points_init)
+    F, J, g, D = lm._linearize(st, sc.obs_cam, sc.obs_pt, px, "huber", SCALE, bf)
+    assert abs(out["cost"] - F) <= 1e-12 * F
+    assert rel(out["grad"].cpu(), g) <= 1e-12
+    assert rel(out["diag"].cpu(), D) <= 1e-12
+    rng = np.random.default_rng(5)
+    for lam in (1e-6, 1e-2, 1e2):
+        p = rng.normal(size=st.n_params)
+        wv, pap = ba.matvec(lam, t64(p))
+        ref = linear.matvec(J, D, lam, p)
+        assert rel(wv.cpu(), ref) <= 1e-12
+        assert abs(pap - p @ ref) <= 1e-12 * abs(p @ ref)
+    stats = ba.solve(SolveOptions(max_lm_iters=10, pcg_tol=1e-10, max_pcg_iters=2000))
+    assert stats["final_cost"] < stats["initial_cost"]
+    cams, pts = ba.get_params()
+    st1 = camera.State.from_bal(cams.cpu().numpy(), pts.cpu().numpy())
+    opts = lm.LMOptions(loss="huber", loss_scale=SCALE, between=bf)
+    F1 = lm.total_cost(st1, sc.obs_cam, sc.obs_pt, px, opts)
+    assert abs(stats["final_cost"] - F1) <= 1e-10 * F1, (stats["final_cost"], F1)
