@@ -60,10 +60,10 @@ constexpr int kCamBits = 25;         // meta: camera id bits; local point in bit
 constexpr int kNumCUs = 256;
 constexpr int kMaxGroups = 2 * kNumCUs;  // workgroups of the fused product, at most
 
-// Padded camera row of the fused product's input vector: 10 doubles (5 x 16 B)
-// or 12 floats (3 x 16 B).
 // Row of one cold observation outside its workgroup's window: its 9 camera
-// values in the working precision, padded to whole 16-byte stores.
+// values in the working precision; float64 rows are padded to whole 16-byte
+// stores, float32 rows are not (36 bytes: every byte the product writes here
+// is read back once by the camera sums).
 template <typename S>
 struct ColdRow;
 template <>
@@ -72,7 +72,7 @@ struct ColdRow<double> {
 };
 template <>
 struct ColdRow<float> {
-  static constexpr int n = 12;
+  static constexpr int n = 9;
 };
 
 // Camera rows of the recomputed-block product: the rotation as a unit
@@ -81,6 +81,8 @@ struct ColdRow<float> {
 constexpr int kProdCamRow = 20;
 constexpr int kProdCamP = 10;  // offset of p in the row
 
+// Camera row of the product's input vector p with stored blocks: its 9 values
+// padded to 10 doubles (5 x 16 B) or 12 floats (3 x 16 B).
 template <typename S>
 struct CamPad;
 template <>

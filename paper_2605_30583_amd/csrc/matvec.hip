@@ -121,8 +121,9 @@ using u32x4 = unsigned __attribute__((ext_vector_type(4)));
 using u32x3 = unsigned __attribute__((ext_vector_type(3)));
 using u32x2 = unsigned __attribute__((ext_vector_type(2)));
 
-// One cold row at byte offset off: 9 values padded to ColdRow<S>::n (five
-// 16-byte stores in float64, three in float32).
+// One cold row at byte offset off: 9 values, padded to ColdRow<S>::n in
+// float64 (five 16-byte stores); in float32 two 16-byte stores and one
+// 4-byte store (rows 4-byte aligned).
 __device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, const double v[9]) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -132,12 +133,14 @@ __device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, c
 }
 
 __device__ inline void store_cold_row(__amdgpu_buffer_rsrc_t rs, unsigned off, const float v[9]) {
+  static_assert(ColdRow<float>::n == 9, "float32 cold rows are 9 values");
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const u32x4 u = {__float_as_uint(v[4 * i]), __float_as_uint(4 * i + 1 < 9 ? v[4 * i + 1] : 0.f),
-                     __float_as_uint(4 * i + 2 < 9 ? v[4 * i + 2] : 0.f), __float_as_uint(4 * i + 3 < 9 ? v[4 * i + 3] : 0.f)};
+  for (int i = 0; i < 2; ++i) {
+    const u32x4 u = {__float_as_uint(v[4 * i]), __float_as_uint(v[4 * i + 1]), __float_as_uint(v[4 * i + 2]),
+                     __float_as_uint(v[4 * i + 3])};
     __builtin_amdgcn_raw_buffer_store_b128(u, rs, (int)off + 16 * i, 0, 0);
   }
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[8]), rs, (int)off + 32, 0, 0);
 }
 
 // Three consecutive scalars at byte offset off.
