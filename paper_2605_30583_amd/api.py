@@ -239,6 +239,8 @@ class BundleAdjuster:
     def set_timing(self, enable: bool, every: int = 1):
         """Event timing of the fused product (caspar_ba_set_timing): every
         `every`-th launch while enabled."""
+        if enable and int(every) == 0:
+            raise ValueError("every must be at least 1 when timing is enabled")
         check(self._lib.caspar_ba_set_timing(self._h, int(every) if enable else 0))
 
     def get_timing(self):
