@@ -123,7 +123,14 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   const size_t max_cold_rows = nc > p.K ? p.max_cold + (size_t)kMaxGroups * kColdWin : 0;
   take(p.cold_list, max_cold_rows * 4 + 4);
   take(p.cold_off, ((size_t)(nc - p.K) + 1) * 4);
-  take(p.cold_rows, max_cold_rows * kColdRow * 8 + 256);  // single-observation rows, then window rows
+  // single-observation rows (ColdRow<S> each, at most max_cold of them), then
+  // from the next 256-byte boundary the window rows (kColdRow doubles, at
+  // most kMaxGroups * kColdWin of them)
+  const size_t single_row_bytes = prec == CASPAR_FP64 ? ColdRow<double>::n * 8 : ColdRow<float>::n * 4;
+  if (nc > p.K)
+    take(p.cold_rows, align_up(p.max_cold * single_row_bytes) + (size_t)kMaxGroups * kColdWin * kColdRow * 8 + 256);
+  else
+    take(p.cold_rows, 256);
   take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
   take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
   take(p.hot_rows, (size_t)p.G * p.K * 9 * acc_bytes(prec));
