@@ -216,9 +216,9 @@ struct caspar_ba {
   // camera-major data
   int* cm_obs = nullptr;        // [no] internal observation of each camera-major entry
   int* cm_pt = nullptr;         // [no] internal point of each camera-major entry
-  double* cm_px = nullptr;      // [no][2]
+  double* cm_px = nullptr;      // [no][2] camera-major observed pixels (float64 form only)
   void* px_s = nullptr;         // [no][2] float32 copy of px (float32-mixed form)
-  void* cm_px_s = nullptr;      // [no][2] float32 copy of cm_px (float32-mixed form)
+  void* cm_px_s = nullptr;      // [no][2] the same in float32 (float32-mixed form only)
   int* cam_off = nullptr;       // [nc + 1]
   cba::Chunk* chunks = nullptr;
   int* chunk_off = nullptr;     // [nc + 1] chunks of camera c

@@ -114,7 +114,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.cold_lo, (size_t)kMaxGroups * 4);
   take(p.p_cam, (size_t)nc * kProdCamRow * 8);
   take(p.cm_pt, (size_t)no * 4);
-  take(p.cm_px, (size_t)no * 16);
+  take(p.cm_px, prec == CASPAR_FP64 ? (size_t)no * 16 : 16);
   take(p.cm_px_s, prec == CASPAR_FP64 ? 16 : (size_t)no * 8);
   take(p.cam_off, ((size_t)nc + 1) * 4);
   take(p.chunks, p.max_chunks * sizeof(Chunk));
@@ -231,14 +231,17 @@ __global__ void k_fill_obs(int n_tiles, const Tile* __restrict__ tiles,
   cam_vals[s] = s;
 }
 
+// Camera-major point indices and observed pixels, the pixels in the working
+// precision (the float32 kernels never read float64 camera-major pixels).
+template <typename T>
 __global__ void k_fill_cm(int no, const int* __restrict__ cm_obs, const uint64_t* __restrict__ skeys,
-                          const double* __restrict__ px, int* cm_pt, double* cm_px) {
+                          const double* __restrict__ px, int* cm_pt, T* cm_px) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < no) {
     const int s = cm_obs[j];
     cm_pt[j] = (int)(skeys[s] >> kCamBits);
-    cm_px[2 * j] = px[2 * s];
-    cm_px[2 * j + 1] = px[2 * s + 1];
+    cm_px[2 * j] = (T)px[2 * s];
+    cm_px[2 * j + 1] = (T)px[2 * s + 1];
   }
 }
 
@@ -290,13 +293,11 @@ __global__ void k_points_out(int np, const double* __restrict__ X, const int* __
 }
 
 // float32 copies of both pixel orders (float32-mixed form).
-__global__ void k_px_cast(int64_t n, const double2* __restrict__ a, const double2* __restrict__ b,
-                          float2* __restrict__ as, float2* __restrict__ bs) {
+__global__ void k_px_cast(int64_t n, const double2* __restrict__ a, float2* __restrict__ as) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) {
-    const double2 u = a[i], v = b[i];
+    const double2 u = a[i];
     as[i] = make_float2((float)u.x, (float)u.y);
-    bs[i] = make_float2((float)v.x, (float)v.y);
   }
 }
 
@@ -311,13 +312,13 @@ __global__ void k_set_px(int no, const int* __restrict__ s2c, const double* __re
   }
 }
 
-__global__ void k_set_cm_px(int no, const int* __restrict__ cm_obs, const double* __restrict__ px,
-                            double* cm_px) {
+template <typename T>
+__global__ void k_set_cm_px(int no, const int* __restrict__ cm_obs, const double* __restrict__ px, T* cm_px) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < no) {
     const int s = cm_obs[j];
-    cm_px[2 * j] = px[2 * s];
-    cm_px[2 * j + 1] = px[2 * s + 1];
+    cm_px[2 * j] = (T)px[2 * s];
+    cm_px[2 * j + 1] = (T)px[2 * s + 1];
   }
 }
 
@@ -345,12 +346,11 @@ static inline unsigned blocks_for(int64_t n, int threads) {
   return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads);
 }
 
+// Point-major pixels in float32 (float32-mixed form only).
 static void cast_pixels(caspar_ba* h) {
   if (h->prec == CASPAR_FP64 || h->no == 0) return;
   k_px_cast<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, reinterpret_cast<const double2*>(h->px),
-                                                           reinterpret_cast<const double2*>(h->cm_px),
-                                                           static_cast<float2*>(h->px_s),
-                                                           static_cast<float2*>(h->cm_px_s));
+                                                           static_cast<float2*>(h->px_s));
   CBA_LAUNCHED();
 }
 
@@ -550,7 +550,11 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
     tb = cub_bytes;
     CBA_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, tb, (const uint32_t*)keys_a, (uint32_t*)vals_b,
                                                vals_a, cm_obs, no, 0, cam_bits, st));
-    k_fill_cm<<<blocks_for(no, 256), 256, 0, st>>>(no, cm_obs, keys_b, h->px, h->cm_pt, h->cm_px);
+    if (h->prec == CASPAR_FP64)
+      k_fill_cm<double><<<blocks_for(no, 256), 256, 0, st>>>(no, cm_obs, keys_b, h->px, h->cm_pt, h->cm_px);
+    else
+      k_fill_cm<float><<<blocks_for(no, 256), 256, 0, st>>>(no, cm_obs, keys_b, h->px, h->cm_pt,
+                                                            static_cast<float*>(h->cm_px_s));
     CBA_LAUNCHED();
     cast_pixels(h);
   }
@@ -843,7 +847,11 @@ int caspar_ba_set_observations(caspar_ba* h, const double* obs_px) {
   if (h->no) {
     k_set_px<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->obs_s2c, obs_px, h->px);
     CBA_LAUNCHED();
-    k_set_cm_px<<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->cm_obs, h->px, h->cm_px);
+    if (h->prec == CASPAR_FP64)
+      k_set_cm_px<double><<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->cm_obs, h->px, h->cm_px);
+    else
+      k_set_cm_px<float><<<blocks_for(h->no, 256), 256, 0, h->stream>>>(h->no, h->cm_obs, h->px,
+                                                                        static_cast<float*>(h->cm_px_s));
     CBA_LAUNCHED();
     cast_pixels(h);
   }
