@@ -32,7 +32,13 @@ Pins (tests/test_oracle_lm.py): zero-noise problems converge to F ~ 0,
 accepted costs decrease monotonically, the noisy optimum matches the
 chi-square expectation, an independent solver (scipy least_squares on an
 additive angle-axis parametrisation with its own residual) reaches the same
-final cost.
+final cost.  The gain ratio's denominator equals the decrease of the linear
+model 1/2 |r + J delta|^2 with J taken by central differences of the
+residual (for the solver's own steps and for arbitrary steps with their inner
+residual); steps that the linear model predicts to within a percent (a
+zero-noise start near the truth) divide lambda by exactly 3; runs of rejected
+trials multiply it by 2, 4, 8, ..., and after an accepted trial the next
+rejection multiplies it by 2 again.
 """
 from __future__ import annotations
 
@@ -72,6 +78,8 @@ class LMIteration:
     pred: float
     accepted: bool
     inner_iters: int
+    nu: float = 2.0      # nu after the iteration's damping update
+    step: np.ndarray | None = None  # the trial step delta (tangent vector)
 
 
 @dataclasses.dataclass
@@ -111,6 +119,33 @@ def total_cost(state, obs_cam, obs_pt, obs_px, opts: "LMOptions") -> float:
     return F
 
 
+def predicted_decrease(b, delta, r_in, lam, D) -> float:
+    """Decrease of the linear model L(d) = 1/2 |r + J d|^2 from d = 0 to
+    d = delta, written with the inner solve's quantities (reading 5): with
+    b = -J^T r and the inner residual r_in = b - (J^T J + lam D) delta,
+      L(0) - L(delta) = -g^T delta - 1/2 |J delta|^2
+                      = 1/2 (b^T delta + delta^T r_in + lam delta^T D delta).
+    For an exact step r_in = 0."""
+    return 0.5 * float(b @ delta + delta @ r_in + lam * delta @ (D * delta))
+
+
+def damping_update(lam: float, nu: float, rho: float, opts: "LMOptions"):
+    """Section V's quality-based update after Madsen and Nielsen.
+    Returns (accepted, lambda, nu) for the gain ratio rho of a trial:
+    rho > 0 accepts, lambda *= max(1/3, 1 - (2 rho - 1)^3) and nu = 2;
+    otherwise lambda *= nu and nu doubles (capped at nu_max).  lambda is then
+    clamped to [lambda_min, lambda_max]."""
+    if rho > 0.0:
+        lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+        nu = 2.0
+        accepted = True
+    else:
+        lam *= nu
+        nu = min(2.0 * nu, opts.nu_max)
+        accepted = False
+    return accepted, min(max(lam, opts.lambda_min), opts.lambda_max), nu
+
+
 def solve_step(J, D, lam, b, n_cams, n_points, opts: LMOptions):
     """Returns (delta, inner residual b - A delta, inner iterations)."""
     if opts.inner == "dense":
@@ -145,7 +180,7 @@ def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None =
             break
         b = -g
         delta, r_in, k = solve_step(J, D, lam, b, state.n_cams, state.n_points, opts)
-        pred = 0.5 * float(b @ delta + delta @ r_in + lam * delta @ (D * delta))
+        pred = predicted_decrease(b, delta, r_in, lam, D)
         if opts.pred_tol > 0.0 and pred <= opts.pred_tol * F:
             reason = "pred"
             break
@@ -153,16 +188,9 @@ def solve(state: camera.State, obs_cam, obs_pt, obs_px, opts: LMOptions | None =
         Ft = total_cost(trial, obs_cam, obs_pt, obs_px, opts)
         rho = (F - Ft) / pred if (pred > 0.0 and np.isfinite(Ft)) else -np.inf
         lam_used = lam
-        if rho > 0.0:
+        accepted, lam, nu = damping_update(lam, nu, rho, opts)
+        if accepted:
             state = trial
             F, J, g, D = lin(state)
-            lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
-            nu = 2.0
-            accepted = True
-        else:
-            lam *= nu
-            nu = min(2.0 * nu, opts.nu_max)
-            accepted = False
-        lam = min(max(lam, opts.lambda_min), opts.lambda_max)
-        history.append(LMIteration(F, Ft, lam_used, rho, pred, accepted, k))
+        history.append(LMIteration(F, Ft, lam_used, rho, pred, accepted, k, nu, delta))
     return LMResult(state, F0, F, history, lam, reason)

@@ -16,7 +16,11 @@ available here, so scenes of the same structure are synthesised:
   + N(0, 0.05^2); f, k1, k2 exact.
 
 * optionally a fraction of observations with gross outliers: their noise is
-  replaced by N(0, outlier_px^2) (drawn last).
+  replaced by N(0, outlier_px^2) (drawn last);
+* optionally a hard start: the initial value of point 0 is moved a given
+  fraction of the way from its true position toward the centre of the first
+  camera that observes it (no draw), so that the first linear models
+  mispredict the cost and trials get rejected.
 
 Draw order is fixed: k1/k2, points, visibility, noise, perturbations,
 outliers.
@@ -104,7 +108,7 @@ def _matrix_to_angle_axis(R: np.ndarray) -> np.ndarray:
 
 
 def _look_at_frames(n_cams: int, radius: float):
-    """Rotation (rows x, y, z) and translation of cameras on a circle.
+    """Rotation (rows x, y, z), translation and centre of cameras on a circle.
 
     Camera i sits at c_i = radius (cos phi_i, sin phi_i, 0), phi_i = 2 pi i / n.
     Its z axis points away from the origin, so the origin has depth -radius.
@@ -118,7 +122,7 @@ def _look_at_frames(n_cams: int, radius: float):
     y = np.cross(z, x)
     R = np.stack([x, y, z], axis=1)          # rows are the camera axes
     t = -np.einsum("nij,nj->ni", R, c)
-    return R, t
+    return R, t, c
 
 
 def _draw_visibility(rng, n_points, n_cams, k_values, k_probs, cam_weights):
@@ -159,10 +163,11 @@ def make_scene(n_cams: int, n_points: int, seed: int, *, k_values=(4,), k_probs=
                zipf_s: float | None = None, radius: float = 10.0, focal: float = 500.0,
                kdist_std: float = 1e-3, point_half_width: float = 2.0,
                noise_px: float = 1.0, rot_std: float = 0.01, trans_std: float = 0.05,
-               point_std: float = 0.05, outlier_frac: float = 0.0, outlier_px: float = 40.0) -> Scene:
+               point_std: float = 0.05, outlier_frac: float = 0.0, outlier_px: float = 40.0,
+               pull_first_point: float = 0.0) -> Scene:
     """Draw one synthetic scene (see module docstring for the recipe)."""
     rng = np.random.default_rng(seed)
-    R, t = _look_at_frames(n_cams, radius)
+    R, t, centres = _look_at_frames(n_cams, radius)
     kd = rng.normal(0.0, kdist_std, size=(n_cams, 2))
     cams = np.empty((n_cams, 9))
     cams[:, 0:3] = _matrix_to_angle_axis(R)
@@ -187,6 +192,9 @@ def make_scene(n_cams: int, n_points: int, seed: int, *, k_values=(4,), k_probs=
         # pixel errors instead of the ordinary noise
         sel = rng.random(obs_cam.shape[0]) < outlier_frac
         noise[sel] = rng.normal(0.0, outlier_px, size=(int(sel.sum()), 2))
+    if pull_first_point != 0.0:
+        c = centres[obs_cam[0]]              # obs_pt is point-major: obs 0 sees point 0
+        pts0[0] = pts[0] + pull_first_point * (c - pts[0])
     return Scene(cams, pts, obs_cam, obs_pt, noise, cams0, pts0)
 
 

@@ -109,3 +109,121 @@ def test_predicted_decrease_stop_ends_at_the_cost_resolution():
     assert all(h.pred > tol * h_prev for h, h_prev in
                zip(stop.history, [stop.initial_cost] + [h.cost for h in stop.history]))
     assert abs(stop.final_cost - full.final_cost) <= 1e-12 * full.final_cost
+
+
+# ---- gain ratio and damping update (Section V, after Madsen and Nielsen) ----
+
+def _hard_start(seed, n_cams=6, n_points=60):
+    """A small scene whose point 0 starts 90% of the way toward a camera that
+    sees it: the first linear models mispredict the cost badly."""
+    return small_scene(n_cams=n_cams, n_points=n_points, seed=seed, k=3, pull_first_point=0.9)
+
+
+def _fd_model_decrease(state, sc, px, delta):
+    """L(0) - L(delta) for L(d) = 1/2 |r + J d|^2, with J delta taken as the
+    central difference of the residual along the retraction curve
+    s -> state (+) s delta (whose derivative at 0 is J delta), step 1e-5
+    relative to delta, and the result refined by one Richardson step."""
+    r0 = camera.residuals(state, sc.obs_cam, sc.obs_pt, px).ravel()
+
+    def jd(h):
+        rp = camera.residuals(state.retract(h * delta), sc.obs_cam, sc.obs_pt, px).ravel()
+        rm = camera.residuals(state.retract(-h * delta), sc.obs_cam, sc.obs_pt, px).ravel()
+        return (rp - rm) / (2.0 * h)
+
+    h = 1e-5 / max(1.0, float(np.max(np.abs(delta))))
+    Jd = (4.0 * jd(h) - jd(2.0 * h)) / 3.0
+    return 0.5 * float(r0 @ r0) - 0.5 * float((r0 + Jd) @ (r0 + Jd))
+
+
+def _replay_states(st0, history):
+    """The state each iteration started from: accepted steps are retracted."""
+    out, st = [], st0
+    for h in history:
+        out.append(st)
+        if h.accepted:
+            st = st.retract(h.step)
+    return out
+
+
+@pytest.mark.parametrize("inner", ["schur", "pcg"])
+def test_predicted_decrease_equals_the_linear_model_decrease(inner):
+    """The gain ratio's denominator is L(0) - L(delta) of the linear model:
+    checked for every trial of a run with rejections, with J delta from
+    finite differences (not from the oracle's Jacobian), and its ratio with
+    the true decrease is the reported rho."""
+    sc = _hard_start(5)
+    px = observed_pixels(sc)
+    st0 = camera.State.from_bal(sc.cams_init, sc.points_init)
+    res = lm.solve(st0, sc.obs_cam, sc.obs_pt, px,
+                   lm.LMOptions(max_iters=10, lambda0=1e-6, inner=inner, pcg_tol=1e-2))
+    assert not all(h.accepted for h in res.history)
+    for h, st in zip(res.history, _replay_states(st0, res.history)):
+        model = _fd_model_decrease(st, sc, px, h.step)
+        assert abs(h.pred - model) <= 1e-6 * abs(model), (h.pred, model)
+        F = camera.cost(st, sc.obs_cam, sc.obs_pt, px)
+        Ft = camera.cost(st.retract(h.step), sc.obs_cam, sc.obs_pt, px)
+        assert abs(h.rho - (F - Ft) / model) <= 1e-6 * max(1.0, abs(h.rho))
+
+
+def test_predicted_decrease_counts_the_inner_residual():
+    """For a step that is not a Galerkin solution (a random direction) the
+    inner residual's term matters: the formula still gives the model decrease."""
+    from oracle import linear
+    sc = _hard_start(5)
+    px = observed_pixels(sc)
+    st = camera.State.from_bal(sc.cams_init, sc.points_init)
+    r, Jc, Jp = camera.linearize(st, sc.obs_cam, sc.obs_pt, px)
+    J = linear.jacobian_csr(Jc, Jp, sc.obs_cam, sc.obs_pt, sc.n_cams, sc.n_points)
+    D = linear.damping_diagonal(J)
+    b = -linear.gradient(J, r.ravel())
+    delta = 1e-3 * np.random.default_rng(3).normal(size=b.size)
+    lam = 0.7
+    r_in = b - linear.matvec(J, D, lam, delta)
+    model = _fd_model_decrease(st, sc, px, delta)
+    assert abs(delta @ r_in) > 1e-2 * abs(model)      # the term is not negligible here
+    pred = lm.predicted_decrease(b, delta, r_in, lam, D)
+    assert abs(pred - model) <= 1e-6 * abs(model), (pred, model)
+
+
+def test_good_steps_divide_lambda_by_three():
+    """Zero noise, start near the truth: the linear model predicts every
+    resolvable trial to within a percent (rho >= 0.99), and the update then
+    divides lambda by exactly 3."""
+    sc = scene_config("tiny", rot_std=1e-4, trans_std=5e-4, point_std=5e-4)
+    px = observed_pixels(sc, noise_scale=0.0)
+    st0 = camera.State.from_bal(sc.cams_init, sc.points_init)
+    res = lm.solve(st0, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=4, lambda0=1e-2))
+    F = res.initial_cost
+    checked = 0
+    for h, nxt in zip(res.history, res.history[1:]):
+        if h.pred <= 1e-10 * F:
+            break
+        assert h.accepted and h.rho >= 0.99, h.rho
+        assert nxt.lam == pytest.approx(h.lam / 3.0, rel=1e-15)
+        F = h.cost
+        checked += 1
+    assert checked >= 2
+
+
+@pytest.mark.parametrize("seed,lambda0,pattern", [(5, 1e-6, "AArrrrrA"), (3, 1e-2, "AAAAArrArA")])
+def test_rejections_double_nu_and_an_accept_resets_it(seed, lambda0, pattern):
+    """A run of rejected trials multiplies lambda by 2, 4, 8, 16, 32; the
+    first rejection after an accepted trial multiplies it by 2 again."""
+    sc = _hard_start(seed)
+    px = observed_pixels(sc)
+    st0 = camera.State.from_bal(sc.cams_init, sc.points_init)
+    res = lm.solve(st0, sc.obs_cam, sc.obs_pt, px, lm.LMOptions(max_iters=len(pattern), lambda0=lambda0))
+    got = "".join("A" if h.accepted else "r" for h in res.history)
+    assert got == pattern
+    factors = [nxt.lam / h.lam for h, nxt in zip(res.history, res.history[1:])]
+    run = 0
+    for h, f in zip(res.history, factors):
+        if h.accepted:
+            run = 0
+            assert 1.0 / 3.0 - 1e-15 <= f < 2.0
+        else:
+            assert f == [2.0, 4.0, 8.0, 16.0, 32.0][run]
+            run += 1
+        # a decisive decision: far from the threshold rho = 0
+        assert abs(h.rho) > 1e-2
