@@ -253,6 +253,36 @@ def main():
             f"F {st['initial_cost']:.6e} -> {st['final_cost']:.6e}")
         return ba, st, dt, tim
 
+    def time_to_accuracy(handle, st, target, label):
+        """First timed iteration k whose parameters have a float64 cost within
+        1e-9 of target (the float64 run's final cost).  Costs come from
+        re-runs of k iterations from the same start, re-evaluated in float64
+        (accepted costs never increase, so k is found by bisection); the time
+        to reach k is the timed run's host clock at the end of iteration k."""
+        hist = st["history"]
+        thr = target * (1.0 + 1e-9)
+
+        def f64_at(k):
+            handle.set_params(cams0, pts0)
+            handle.solve(SolveOptions(max_lm_iters=k, pcg_tol=a.pcg_tol, grad_tol=0.0, min_cost=0.0))
+            return handle.cost_fp64()
+
+        lo, hi = 1, len(hist)
+        if hi == 0 or f64_at(hi) > thr:
+            return {"reached": False, "within": 1e-9, "of": "float64 run's final cost"}
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if f64_at(mid) <= thr:
+                hi = mid
+            else:
+                lo = mid + 1
+        sec = hist[lo - 1]["seconds"]
+        log(f"{label}: cost within 1e-9 of the float64 final at iteration {lo}, {sec:.3f}s")
+        return {"reached": True, "iteration": lo, "seconds": sec, "lm_iters_per_s": lo / sec, "within": 1e-9,
+                "of": "float64 run's final cost",
+                "how": "float64 cost of re-runs of k iterations from the same start (bisection over k); seconds "
+                       "from the timed run's per-iteration host clock"}
+
     ba, st, dt, tim = timed_solve(prec, a.precision)
     iters = st["lm_iters"]
     value = iters / dt
@@ -262,9 +292,11 @@ def main():
     f_primary = ba.cost_fp64()
 
     extra = {}
+    f_ref = None
     if prec == FP32_MIXED and not a.no_fp64:
         ba64, st64, dt64, tim64 = timed_solve(FP64, "fp64")
         f64 = ba64.cost_fp64()
+        f_ref = f64
         mv64 = tim64["matvec_ms"] / max(1, tim64["matvec_launches"])
         extra["fp64"] = {
             "lm_iters_per_s": st64["lm_iters"] / dt64,
@@ -274,6 +306,7 @@ def main():
             "matvec_gbs": tim64["matvec_bytes"] / (mv64 * 1e-3) / 1e9 if tim64["matvec_launches"] else None,
         }
         extra["fp32_mixed_cost_rel_error_vs_fp64"] = (f_primary - f64) / f64
+        extra["fp64"]["time_to_accuracy"] = time_to_accuracy(ba64, st64, f_ref, "fp64")
         del ba64
         torch.cuda.empty_cache()
 
@@ -294,6 +327,9 @@ def main():
             "matvec_frac_of_copy": gbs_alt / copy["gbs"],
             "matvec_tflops": FLOPS_PER_OBS[alt] * sc.n_obs / (mv_alt * 1e-3) / 1e12,
         }
+        if f_ref is not None:
+            extra[f"{alt}_jacobian"]["time_to_accuracy"] = time_to_accuracy(ba_alt, st_alt, f_ref,
+                                                                             f"{a.precision}/{alt}")
         del ba_alt
         torch.cuda.empty_cache()
 
@@ -328,13 +364,35 @@ def main():
         torch.cuda.empty_cache()
 
     if not a.no_adjoint:
-        _, pts = ba.get_params()
+        # backward at the headline solve's optimum (its own precision), then
+        # the same backward in float64 at the same parameters as its reference
+        cams_s, pts = ba.get_params()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g = ba.backward(None, 2.0 * pts, lambda_adj=1e-4, pcg_tol=1e-6, max_pcg_iters=500)
         torch.cuda.synchronize()
         extra["adjoint"] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": ba.last_backward_iters,
+                            "pcg_rel_resid": ba.last_backward_rel_resid, "lambda_adj": 1e-4, "pcg_tol": 1e-6,
                             "loss": "sum of squared optimal point coordinates", "grad_norm": float(g.norm())}
+        if prec == FP32_MIXED and not a.no_fp64:
+            ba_ref = BundleAdjuster(cams_s, pts, oc, op, px, FP64, recompute_jacobian=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g64 = ba_ref.backward(None, 2.0 * pts, lambda_adj=1e-4, pcg_tol=1e-10, max_pcg_iters=5000)
+            torch.cuda.synchronize()
+            extra["adjoint"]["fp64_reference"] = {
+                "ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": ba_ref.last_backward_iters,
+                "pcg_tol": 1e-10, "pcg_rel_resid": ba_ref.last_backward_rel_resid}
+            extra["adjoint"]["rel_error_vs_fp64"] = float((g - g64).norm() / g64.norm())
+            log(f"adjoint: float32-mixed vs float64 relative error {extra['adjoint']['rel_error_vs_fp64']:.3e}")
+            del ba_ref, g64
+            torch.cuda.empty_cache()
+
+    if f_ref is not None:
+        # after the adjoint, which needs the headline handle at its optimum
+        tta = time_to_accuracy(ba, st, f_ref, a.precision)
+    else:
+        tta = None
 
     if a.jacobian == "stored":
         # the blocks stream from HBM: priced on the bytes the product must move
@@ -377,6 +435,7 @@ def main():
             "parallelism": "single GPU",
         },
         "create_seconds": create_s[a.precision],
+        "time_to_accuracy": tta,
         "roofline": roofline,
     }
     line["hbm_copy"] = copy

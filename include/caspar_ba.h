@@ -60,11 +60,16 @@ enum { CASPAR_FP64 = 0, CASPAR_FP32_MIXED = 1 };
  * workspace_bytes.  By default the linearisation stores the 2x9 / 2x3 blocks
  * of every observation and each normal-equation product streams them from
  * HBM.  With CASPAR_RECOMPUTE_JACOBIAN nothing per observation is stored
- * beyond its indices: every product (and the adjoint) evaluates the blocks
- * again from the camera row and the point coordinates, trading about 70
- * arithmetic operations per observation for 96 (float32) or 192 (float64)
- * bytes of HBM traffic.  Results are identical up to rounding order; the
- * blocks are bitwise the same as the stored ones. */
+ * beyond its indices: every product (and the adjoint) applies the blocks in
+ * factored form from the camera row (rotation as a unit quaternion,
+ * translation, calibration) and the point coordinates, without forming
+ * them: 184 floating-point operations per observation instead of the 100
+ * of applying stored blocks, against 96 (float32) or 192 (float64) bytes
+ * of HBM traffic saved.  The map is the same linear operator; the results
+ * agree with the stored-block ones to rounding (the rotation is rebuilt
+ * from the quaternion), not bit for bit.  Sec. V notes that the generated
+ * kernels exploit sparse and partially linear blocks; this is that idea
+ * applied to the product. */
 enum { CASPAR_RECOMPUTE_JACOBIAN = 0x10 };
 
 /* Robust losses of the squared residual norm s = |r_o|^2 (caspar_ba_set_loss).
@@ -127,11 +132,19 @@ typedef struct caspar_iter_record {
   double pcg_rel_resid; /* ||r_pcg|| / ||b|| at exit */
   int32_t accepted;
   int32_t pcg_iters;
+  double seconds;     /* host wall time from the start of the solve to the end of this
+                         iteration (includes the relinearisation of an accepted step) */
 } caspar_iter_record;
 
+/* Fills opts with the defaults listed above (Sec. V solver, Sec. VI
+ * settings: damping 1 / 100, CG tolerance 1e-3).  opts (host) must not be
+ * NULL. */
 CASPAR_API void caspar_default_solve_opts(caspar_solve_opts* opts);
 
 /* Bytes of device workspace a handle of this size needs (0 on bad sizes).
+ * Sec. V: the solver works in one block of GPU memory for the whole
+ * optimisation, every array a view into it; here the caller allocates that
+ * block and passes it to create().
  * n_obs must be < 2^31, n_cams < 2^25 and 3 n_points scalars (float64 or
  * float32 by precision) under 2 GiB.  mode = precision | Jacobian flag. */
 CASPAR_API size_t caspar_ba_workspace_bytes(int32_t n_cams, int32_t n_points, int64_t n_obs, int mode);
@@ -152,6 +165,26 @@ CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_point
                      const int32_t* obs_pt, const double* obs_px, int mode,
                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* create() without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The handle's workspace is a static
+ * device array of the library, 256 MiB (268435456 bytes), which every GPU the
+ * library runs on holds until the process ends; the call makes no device or
+ * pinned-host allocation (scalar read-backs go through the handle's own host
+ * memory, so solves poll a little slower than with create()).  Problems
+ * whose caspar_ba_workspace_bytes() exceeds 256 MiB get CASPAR_ENOMEM (about
+ * a million observations in CASPAR_FP32_MIXED | CASPAR_RECOMPUTE_JACOBIAN
+ * mode; fewer with stored blocks or float64).  The array belongs to one
+ * handle at a time on each GPU: while a handle created this way lives, a
+ * second call on the same GPU returns CASPAR_EINVAL (destroy the first);
+ * caspar_ba_destroy releases it.  The contents left by the previous handle
+ * are overwritten by create, as with a fresh workspace.  Every other argument
+ * and every later call on the handle behave as with caspar_ba_create on the
+ * current device. */
+CASPAR_API int caspar_ba_create_static(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                                       const double* cams, const double* points, const int32_t* obs_cam,
+                                       const int32_t* obs_pt, const double* obs_px, int mode, void* hip_stream);
+
 /* Run Levenberg-Marquardt from the current parameters (Sec. V).  opts may be
  * NULL (defaults).  stats (host) may be NULL; history (host) may be NULL or
  * hold opts->max_lm_iters records.  The parameters afterwards are the last
@@ -159,13 +192,14 @@ CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_point
 CASPAR_API int caspar_ba_solve(caspar_ba* h, const caspar_solve_opts* opts, caspar_solve_stats* stats,
                     caspar_iter_record* history);
 
-/* Current parameters in BAL layout, caller order (dev outputs; either may be
- * NULL). */
+/* Current parameters (the nodes of the Sec. VI-A problem: camera poses with
+ * their calibration, and points) in BAL layout, caller order (dev outputs;
+ * either may be NULL). */
 CASPAR_API int caspar_ba_get_params(caspar_ba* h, double* cams, double* points);
 
-/* Replace the parameters (dev inputs, BAL, caller order; either may be NULL
- * to keep that part).  Use with lambda0 = the last final_lambda for a warm
- * restart. */
+/* Replace the parameters (the nodes of the Sec. VI-A problem; dev inputs,
+ * BAL, caller order; either may be NULL to keep that part).  Use with
+ * lambda0 = the last final_lambda for a warm restart of the Sec. V solver. */
 CASPAR_API int caspar_ba_set_params(caspar_ba* h, const double* cams, const double* points);
 
 /* Select the robust loss (default CASPAR_LOSS_TRIVIAL).  The cost becomes
@@ -180,31 +214,42 @@ CASPAR_API int caspar_ba_set_params(caspar_ba* h, const double* cams, const doub
  * be finite and > 0 (CASPAR_EINVAL otherwise, or for an unknown kind). */
 CASPAR_API int caspar_ba_set_loss(caspar_ba* h, int32_t kind, double scale);
 
-/* Replace the observed pixels (dev [n_obs][2], caller order). */
+/* Replace the observed pixels, the measurements of the Sec. VI-A
+ * reprojection factors (dev [n_obs][2], caller order); the structure (which
+ * camera sees which point) is kept.  CASPAR_EINVAL for a non-finite value. */
 CASPAR_API int caspar_ba_set_observations(caspar_ba* h, const double* obs_px);
 
-/* Implicit adjoint of the optimum with respect to the observed pixels.
- * With g the tangent gradient of a loss L(cameras*, points*), solve
- * (J^T J + lambda_adj D) v = g by the same block-Jacobi PCG and write
+/* Implicit adjoint of the optimum with respect to the observed pixels: the
+ * implicit function theorem applied to the fixed point that the solver of
+ * Sec. V converges to, J^T r = 0 at the optimum, with the Gauss-Newton
+ * matrix of that solver (second-order residual terms dropped) and its
+ * damping.  With g the tangent gradient of a loss L(cameras*, points*),
+ * solve (J^T J + lambda_adj D) v = g by the same block-Jacobi PCG and write
  * dL/dpx_o = J_o v (dev [n_obs][2], caller order), since dr/dpx = -I.
  * grad_cams (dev [n_cams][9], BAL: gradient w.r.t. the angle-axis vector,
  * translation, f, k1, k2; may be NULL = 0) is mapped to the right tangent
  * with the inverse right Jacobian of SO(3); grad_points (dev [n_points][3],
- * may be NULL = 0).  J and D are those of the current parameters.
+ * may be NULL = 0).  J and D are those of the current parameters.  In
+ * CASPAR_FP32_MIXED mode v and the PCG vectors are float32 (dots float64),
+ * as in the forward solve.
  * flags: CASPAR_ADJ_GAUGE_PROJECT removes the D-weighted component of g
  * along the 7 similarity-gauge directions N (world rotation, translation,
  * scale): g <- g - D N (N^T D N)^-1 N^T g.  Because J N = 0 and
  * A N = lambda_adj D N this leaves J A^-1 g unchanged, and it keeps v free
  * of the 1/lambda_adj gauge component, so small lambda_adj stay well
- * conditioned.  pcg_iters (host, may be NULL) receives the iteration count. */
+ * conditioned.  pcg_iters and rel_resid (host, each may be NULL) receive the
+ * iteration count and ||g - A v|| / ||g|| of the PCG recurrence at exit:
+ * a rel_resid above pcg_tol means the solve stopped at max_pcg_iters and the
+ * gradient is correspondingly inexact (the call still succeeds). */
 enum { CASPAR_ADJ_GAUGE_PROJECT = 1 };
 CASPAR_API int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points,
                        double lambda_adj, double pcg_tol, int32_t max_pcg_iters, int32_t flags,
-                       double* grad_obs_px, int32_t* pcg_iters);
+                       double* grad_obs_px, int32_t* pcg_iters, double* rel_resid);
 
 /* ---- Parity hooks: single steps of the hot path at the current parameters ---- */
 
-/* Linearise (residuals, Jacobian blocks, cost, gradient g = J^T r, damping
+/* Linearise as the Sec. V solver does at each accepted step: the
+ * tangent-space Jacobian blocks of the Sec. VI-A factor (residuals, Jacobian blocks, cost, gradient g = J^T r, damping
  * diagonal D = clamp(diag J^T J, 1e-6, 1e32)); with a robust loss the
  * residuals and blocks are the sqrt(w)-scaled ones and the cost is
  * 1/2 sum rho(|r|^2) (see caspar_ba_set_loss).  cost (host) may be NULL;
@@ -214,38 +259,47 @@ CASPAR_API int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const d
 CASPAR_API int caspar_ba_linearize(caspar_ba* h, double* cost, double* resid, double* jac_cam,
                         double* jac_pt, double* grad, double* diag);
 
-/* w = (J^T J + lambda D) p with J, D of the last linearisation (linearises
+/* The damped normal-equation product the Sec. V solver's PCG applies without
+ * forming J^T J or a Schur complement:
+ * w = (J^T J + lambda D) p with J, D of the last linearisation (linearises
  * first if the parameters changed).  p, w (dev [N]); pAp (host, may be NULL)
  * receives p^T w as accumulated by the fused kernel. */
 CASPAR_API int caspar_ba_matvec(caspar_ba* h, double lambda, const double* p, double* w, double* pAp);
 
-/* z = M^-1 r with M the block diagonal of J^T J + lambda D (dev [N]). */
+/* The block-Jacobi preconditioner of Sec. V, one block per node (a 9x9 block
+ * per camera, a 3x3 block per point): z = M^-1 r with M the block diagonal
+ * of J^T J + lambda D (dev [N]). */
 CASPAR_API int caspar_ba_block_jacobi_apply(caspar_ba* h, double lambda, const double* r, double* z);
 
-/* PCG on (J^T J + lambda D) x = b from x = 0 (dev [N]); iters and rel_resid
+/* The inner solve of Sec. V, block-Jacobi preconditioned conjugate gradients
+ * on the normal equations:
+ * PCG on (J^T J + lambda D) x = b from x = 0 (dev [N]); iters and rel_resid
  * (host, may be NULL) receive the iteration count and ||r||/||b|| of the
  * recurrence residual. */
 CASPAR_API int caspar_ba_pcg(caspar_ba* h, double lambda, const double* b, double tol, int32_t max_iters,
                   double* x, int32_t* iters, double* rel_resid);
 
-/* Cost F = 1/2 sum |r|^2 at the current parameters, accumulated in float64
+/* The objective the Sec. V solver minimises over the Sec. VI-A factors:
+ * cost F = 1/2 sum |r|^2 at the current parameters, accumulated in float64
  * from residuals evaluated in float64 regardless of the handle's precision
  * (host out). */
 CASPAR_API int caspar_ba_cost_fp64(caspar_ba* h, double* cost);
 
-/* Predicted pixels of the Snavely model for arbitrary parameters, float64,
+/* Predicted pixels of the Snavely model (Sec. VI-A) for arbitrary parameters, float64,
  * no handle needed (dev in/out, caller layout).  hip_stream may be NULL. */
 CASPAR_API int caspar_project(int32_t n_cams, int32_t n_points, int64_t n_obs, const double* cams,
                    const double* points, const int32_t* obs_cam, const int32_t* obs_pt,
                    double* px_out, void* hip_stream);
 
-/* Sizes of the internal layout (host outs, any may be NULL): the number of
+/* Sizes of the internal layout (host outs, any may be NULL; a helper for
+ * measurement, no passage of the paper defines it): the number of
  * cameras accumulated in LDS by the fused product, observations of the other
  * cameras, wave tiles, and workgroups of the fused product. */
 CASPAR_API int caspar_ba_layout_info(caspar_ba* h, int32_t* hot_cams, int64_t* cold_obs, int64_t* n_tiles,
                           int32_t* matvec_groups);
 
-/* Kernel timing for roofline reporting.  While enabled, every k-th launch of
+/* Kernel timing for roofline reporting (Sec. VI compares solvers by time;
+ * this times the product that dominates it).  While enabled, every k-th launch of
  * the fused normal-equation product made by solve/pcg/backward/matvec
  * (counted across solves, so every position inside a solve is sampled) is
  * timed by HIP events on the handle's stream that the launch itself stamps;
@@ -268,6 +322,9 @@ typedef struct caspar_timing {
 CASPAR_API int caspar_ba_set_timing(caspar_ba* h, int enable);
 CASPAR_API int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out);
 
+/* Release the handle (its pinned host read-back buffer and HIP events; the
+ * caller's workspace is untouched and may be freed afterwards).  NULL is a
+ * no-op. */
 CASPAR_API void caspar_ba_destroy(caspar_ba* h);
 
 /* Pose between-factors: a second factor type on pairs of cameras (the

@@ -31,7 +31,7 @@ class SolveStats(C.Structure):
 class IterRecord(C.Structure):
     _fields_ = [("cost", C.c_double), ("trial_cost", C.c_double), ("lam", C.c_double), ("rho", C.c_double),
                 ("pred", C.c_double), ("pcg_rel_resid", C.c_double), ("accepted", C.c_int32),
-                ("pcg_iters", C.c_int32)]
+                ("pcg_iters", C.c_int32), ("seconds", C.c_double)]
 
 
 class Timing(C.Structure):
@@ -46,13 +46,15 @@ SIGNATURES = [
     ("caspar_ba_workspace_bytes", C.c_size_t, [C.c_int32, C.c_int32, C.c_int64, C.c_int]),
     ("caspar_ba_create", C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int,
                                    _P, C.c_size_t, _P]),
+    ("caspar_ba_create_static", C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
+                                          C.c_int, _P]),
     ("caspar_ba_solve", C.c_int, [_P, C.POINTER(SolveOpts), C.POINTER(SolveStats), C.POINTER(IterRecord)]),
     ("caspar_ba_get_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_observations", C.c_int, [_P, _P]),
     ("caspar_ba_set_loss", C.c_int, [_P, C.c_int32, C.c_double]),
     ("caspar_ba_backward", C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, C.c_int32, _P,
-                                     C.POINTER(C.c_int32)]),
+                                     C.POINTER(C.c_int32), _D]),
     ("caspar_ba_linearize", C.c_int, [_P, _D, _P, _P, _P, _P, _P]),
     ("caspar_ba_matvec", C.c_int, [_P, C.c_double, _P, _P, _D]),
     ("caspar_ba_block_jacobi_apply", C.c_int, [_P, C.c_double, _P, _P]),

@@ -72,7 +72,10 @@ class BundleAdjuster:
     """One problem on one GPU (a caspar_ba handle plus its workspace)."""
 
     def __init__(self, cams, points, obs_cam, obs_pt, obs_px, precision: int = FP64,
-                 recompute_jacobian: bool = False):
+                 recompute_jacobian: bool = False, static_workspace: bool = False):
+        """static_workspace: build the handle on the library's static device
+        array (caspar_ba_create_static) instead of a workspace allocated here;
+        one such handle per GPU at a time, problems up to 256 MiB of workspace."""
         lib = _native.load()
         self._lib = lib
         self.n_cams, self.n_points, self.n_obs = int(cams.shape[0]), int(points.shape[0]), int(obs_cam.shape[0])
@@ -85,6 +88,14 @@ class BundleAdjuster:
         _dev(obs_cam, torch.int32, (self.n_obs,), "obs_cam")
         _dev(obs_pt, torch.int32, (self.n_obs,), "obs_pt")
         _dev(obs_px, torch.float64, (self.n_obs, 2), "obs_px")
+        h = C.c_void_p()
+        if static_workspace:
+            self.workspace = None
+            check(lib.caspar_ba_create_static(C.byref(h), self.n_cams, self.n_points, self.n_obs, _ptr(cams),
+                                              _ptr(points), _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), mode,
+                                              _stream()))
+            self._h = h
+            return
         nbytes = lib.caspar_ba_workspace_bytes(self.n_cams, self.n_points, self.n_obs, mode)
         if nbytes == 0:
             raise ValueError("unsupported problem size or precision")
@@ -93,7 +104,6 @@ class BundleAdjuster:
         off = (-base) % 256
         self._ws_ptr = C.c_void_p(base + off)
         self._ws_bytes = nbytes
-        h = C.c_void_p()
         check(lib.caspar_ba_create(C.byref(h), self.n_cams, self.n_points, self.n_obs, _ptr(cams), _ptr(points),
                                    _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), mode, self._ws_ptr,
                                    self._ws_bytes, _stream()))
@@ -224,16 +234,27 @@ class BundleAdjuster:
 
     def backward(self, grad_cams=None, grad_points=None, lambda_adj=1e-4, pcg_tol=1e-10, max_pcg_iters=2000,
                  gauge_project=False):
+        """dL/dpx (caspar_ba_backward).  The adjoint PCG's iteration count and
+        relative residual are kept in last_backward_iters and
+        last_backward_rel_resid; a solve that stopped at max_pcg_iters above
+        pcg_tol raises a RuntimeWarning."""
         if grad_cams is not None:
             _dev(grad_cams, torch.float64, (self.n_cams, 9), "grad_cams")
         if grad_points is not None:
             _dev(grad_points, torch.float64, (self.n_points, 3), "grad_points")
         out = torch.empty((self.n_obs, 2), dtype=torch.float64, device=self.device)
         it = C.c_int32()
+        rr = C.c_double()
         flags = _native.ADJ_GAUGE_PROJECT if gauge_project else 0
         check(self._lib.caspar_ba_backward(self._h, _ptr(grad_cams), _ptr(grad_points), float(lambda_adj),
-                                           float(pcg_tol), int(max_pcg_iters), flags, _ptr(out), C.byref(it)))
+                                           float(pcg_tol), int(max_pcg_iters), flags, _ptr(out), C.byref(it),
+                                           C.byref(rr)))
         self.last_backward_iters = it.value
+        self.last_backward_rel_resid = rr.value
+        if rr.value > pcg_tol:
+            import warnings
+            warnings.warn(f"adjoint PCG stopped after {it.value} iterations at relative residual {rr.value:.3e} "
+                          f"> pcg_tol {pcg_tol:.3e}; the gradient is inexact", RuntimeWarning, stacklevel=2)
         return out
 
     def set_timing(self, enable: bool, every: int = 1):
@@ -328,6 +349,7 @@ class BAFunction(torch.autograd.Function):
         lam, tol, iters = ctx.adj
         gc = None if grad_cams is None else grad_cams.contiguous().to(torch.float64)
         gp = None if grad_points is None else grad_points.contiguous().to(torch.float64)
+        # the handle stays open (freed with ctx), so a second backward of a
+        # retained graph works
         g_obs = ctx.ba.backward(gc, gp, lam, tol, iters)
-        ctx.ba.close()
         return g_obs, None, None, None, None, None, None, None, None, None, None

@@ -17,8 +17,11 @@
 //  * points are contiguous inside a tile: an in-wave segmented scan sums their
 //    contributions and the first lane of each point writes w_j directly.
 // A second small kernel adds the per-workgroup rows and cold rows of each
-// camera (fixed order: deterministic), handles split and orphan points and
-// turns the p^T A p partials into alpha for PCG.
+// camera in a fixed order, handles split and orphan points and turns the
+// p^T A p partials into alpha for PCG.  The LDS sums themselves are atomic
+// adds in the order the waves happen to reach them, so the camera side of w
+// (and with it every later PCG iterate) varies from run to run at the
+// rounding level; the point side and the fixed-order second pass do not.
 #include <hip/hip_ext.h>
 
 #include <mutex>

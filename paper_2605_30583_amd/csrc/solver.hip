@@ -259,6 +259,7 @@ static void solve_impl(caspar_ba* h, const caspar_solve_opts* opts_in, caspar_so
       r.pcg_rel_resid = rel;
       r.accepted = acc ? 1 : 0;
       r.pcg_iters = k;
+      r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     }
     ++iters;
   }
@@ -498,7 +499,7 @@ int caspar_ba_get_timing(caspar_ba* h, caspar_timing* out) {
 
 int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad_points, double lambda_adj,
                        double pcg_tol, int32_t max_pcg_iters, int32_t flags, double* grad_obs_px,
-                       int32_t* pcg_iters) {
+                       int32_t* pcg_iters, double* rel_resid) {
   CBA_API_BEGIN
   CBA_REQUIRE(h != nullptr, "handle is NULL");
   CBA_REQUIRE(h->no == 0 || grad_obs_px != nullptr, "grad_obs_px is NULL");
@@ -528,6 +529,7 @@ int caspar_ba_backward(caspar_ba* h, const double* grad_cams, const double* grad
     adjoint_obs_t<float>(h, grad_obs_px);
   sync(h);
   if (pcg_iters) *pcg_iters = k;
+  if (rel_resid) *rel_resid = rel;
   CBA_API_END
 }
 

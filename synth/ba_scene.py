@@ -211,6 +211,10 @@ SCENE_CONFIGS = {
     # robust losses: the tiny scene with 5% gross outliers (40 px)
     "tiny_outliers": dict(n_cams=16, n_points=1_000, seed=1, k_values=(4,), k_probs=(1.0,),
                           outlier_frac=0.05, outlier_px=40.0),
+    # damping-rule trajectories: six cameras, 60 points, point 0 starting 90%
+    # of the way toward a camera that sees it (rejected trials early on)
+    "hard_start_a": dict(n_cams=6, n_points=60, seed=5, k_values=(3,), k_probs=(1.0,), pull_first_point=0.9),
+    "hard_start_b": dict(n_cams=6, n_points=60, seed=3, k_values=(3,), k_probs=(1.0,), pull_first_point=0.9),
 }
 
 

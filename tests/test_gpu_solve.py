@@ -128,3 +128,27 @@ def test_autograd_function_backward():
     ref = adjoint.implicit_grad_obs(state, sc.obs_cam, sc.obs_pt, px.detach().cpu().numpy(),
                                     adjoint.point_norm_loss_grad(state), 1e-4, "schur")
     assert rel(px.grad.cpu().numpy(), ref) <= 1e-6
+
+
+def test_autograd_function_second_backward_of_a_retained_graph():
+    from paper_2605_30583_amd import BAFunction, SolveOptions
+    sc = scene_config("tiny")
+    px = t64(observed_pixels(sc)).requires_grad_(True)
+    cams, pts = BAFunction.apply(px, t64(sc.cams_init), t64(sc.points_init), t32i(sc.obs_cam), t32i(sc.obs_pt),
+                                 SolveOptions(max_lm_iters=20, pcg_tol=1e-6), 0, 1e-4, 1e-12, 5000)
+    loss = (pts * pts).sum()
+    loss.backward(retain_graph=True)
+    first = px.grad.clone()
+    loss.backward()
+    assert rel(px.grad.cpu().numpy(), 2.0 * first.cpu().numpy()) <= 1e-12
+
+
+def test_backward_reports_an_unconverged_adjoint_solve():
+    sc, px, ba, st = _solve("tiny")
+    _, pts = ba.get_params()
+    with pytest.warns(RuntimeWarning, match="adjoint PCG stopped"):
+        ba.backward(None, 2.0 * pts, lambda_adj=1e-4, pcg_tol=1e-12, max_pcg_iters=2)
+    assert ba.last_backward_iters == 2
+    assert ba.last_backward_rel_resid > 1e-12
+    ba.backward(None, 2.0 * pts, lambda_adj=1e-4, pcg_tol=1e-12, max_pcg_iters=5000)
+    assert ba.last_backward_rel_resid <= 1e-12
