@@ -32,7 +32,7 @@ RUNS = {
     "tiny_outliers_cauchy": ("tiny_outliers", 40, "cauchy", 3.0, None, 1e-2),
     "tiny_between": ("tiny", 20, "trivial", 1.0, BETWEEN, 1e-2),
     # runs with rejected trials: the damping rule's growth and reset
-    "hard_start_a": ("hard_start_a", 12, "trivial", 1.0, None, 1e-6),
+    "hard_start_a": ("hard_start_a", 12, "trivial", 1.0, None, 1e-3),
     "hard_start_b": ("hard_start_b", 12, "trivial", 1.0, None, 1e-2),
 }
 

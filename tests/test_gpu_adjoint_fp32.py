@@ -7,15 +7,17 @@ Tolerance.  At the optimum of `tiny` the block-Jacobi preconditioned matrix
 M^-1 (J^T J + lambda D) at lambda_adj = 1e-4 has its seven gauge eigenvalues
 near lambda_adj and the rest in [0.087, 2.0] (float64 eigenvalues of the
 dense matrix), a condition number of 23 off the gauge.  J v does not see the
-gauge part of v (J N = 0), so the error of dL/dpx is that of a
+gauge part of v (J N = 0), so with the gauge projection (which removes that
+part from the right-hand side) the error of dL/dpx is that of a
 well-conditioned solve: the float32 blocks carry a relative error of a few
 u = 2^-24 from their evaluation (about ten roundings along the chain), which
 the solve amplifies by at most the condition number, 23 * 10 u = 1.4e-5, plus
-the PCG stopping residual (tolerance 1e-6, also amplified by at most 23).
-Without the gauge projection v also holds a gauge component about 1/lambda_adj
-times larger than the rest, whose product with the float32 blocks is not
-exactly zero: u |J| |v_N| adds a rounding residue, so that case gets twice the
-bound.  Bars: 5e-5 with the projection, 1e-4 without."""
+the PCG stopping residual (tolerance 1e-6, also amplified by at most 23):
+bar 5e-5.  Without the projection v also holds the gauge component, about
+sigma / lambda_adj = 0.087 / 1e-4 = 870 times the size of the rest (sigma: the
+smallest eigenvalue off the gauge), and float32 blocks do not annihilate it
+exactly: J v picks up a rounding residue of about 10 u |J| |v_N|, relative
+10 u * 870 = 5.2e-4 of J v: bar 5e-4."""
 import numpy as np
 import pytest
 
@@ -54,4 +56,4 @@ def test_fp32_mixed_adjoint_matches_oracle(name, rj, gauge):
     print(f"{name} rj={rj} gauge={gauge}: float32-mixed adjoint relative error {err:.3e}, "
           f"PCG {ba.last_backward_iters} iterations, residual {ba.last_backward_rel_resid:.2e}")
     assert ba.last_backward_rel_resid <= 1e-6
-    assert err <= (5e-5 if gauge else 1e-4)
+    assert err <= (5e-5 if gauge else 5e-4)
