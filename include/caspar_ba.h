@@ -165,6 +165,26 @@ CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_point
                      const int32_t* obs_pt, const double* obs_px, int mode,
                      void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* create() without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The handle's workspace is a static
+ * device array of the library, 256 MiB (268435456 bytes), which every GPU the
+ * library runs on holds until the process ends; the call makes no device or
+ * pinned-host allocation (scalar read-backs go through the handle's own host
+ * memory, so solves poll a little slower than with create()).  Problems
+ * whose caspar_ba_workspace_bytes() exceeds 256 MiB get CASPAR_ENOMEM (about
+ * a million observations in CASPAR_FP32_MIXED | CASPAR_RECOMPUTE_JACOBIAN
+ * mode; fewer with stored blocks or float64).  The array belongs to one
+ * handle at a time on each GPU: while a handle created this way lives, a
+ * second call on the same GPU returns CASPAR_EINVAL (destroy the first);
+ * caspar_ba_destroy releases it.  The contents left by the previous handle
+ * are overwritten by create, as with a fresh workspace.  Every other argument
+ * and every later call on the handle behave as with caspar_ba_create on the
+ * current device. */
+CASPAR_API int caspar_ba_create_static(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                                       const double* cams, const double* points, const int32_t* obs_cam,
+                                       const int32_t* obs_pt, const double* obs_px, int mode, void* hip_stream);
+
 /* Run Levenberg-Marquardt from the current parameters (Sec. V).  opts may be
  * NULL (defaults).  stats (host) may be NULL; history (host) may be NULL or
  * hold opts->max_lm_iters records.  The parameters afterwards are the last

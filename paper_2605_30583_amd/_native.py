@@ -46,6 +46,8 @@ SIGNATURES = [
     ("caspar_ba_workspace_bytes", C.c_size_t, [C.c_int32, C.c_int32, C.c_int64, C.c_int]),
     ("caspar_ba_create", C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int,
                                    _P, C.c_size_t, _P]),
+    ("caspar_ba_create_static", C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
+                                          C.c_int, _P]),
     ("caspar_ba_solve", C.c_int, [_P, C.POINTER(SolveOpts), C.POINTER(SolveStats), C.POINTER(IterRecord)]),
     ("caspar_ba_get_params", C.c_int, [_P, _P, _P]),
     ("caspar_ba_set_params", C.c_int, [_P, _P, _P]),

@@ -72,7 +72,10 @@ class BundleAdjuster:
     """One problem on one GPU (a caspar_ba handle plus its workspace)."""
 
     def __init__(self, cams, points, obs_cam, obs_pt, obs_px, precision: int = FP64,
-                 recompute_jacobian: bool = False):
+                 recompute_jacobian: bool = False, static_workspace: bool = False):
+        """static_workspace: build the handle on the library's static device
+        array (caspar_ba_create_static) instead of a workspace allocated here;
+        one such handle per GPU at a time, problems up to 256 MiB of workspace."""
         lib = _native.load()
         self._lib = lib
         self.n_cams, self.n_points, self.n_obs = int(cams.shape[0]), int(points.shape[0]), int(obs_cam.shape[0])
@@ -85,6 +88,14 @@ class BundleAdjuster:
         _dev(obs_cam, torch.int32, (self.n_obs,), "obs_cam")
         _dev(obs_pt, torch.int32, (self.n_obs,), "obs_pt")
         _dev(obs_px, torch.float64, (self.n_obs, 2), "obs_px")
+        h = C.c_void_p()
+        if static_workspace:
+            self.workspace = None
+            check(lib.caspar_ba_create_static(C.byref(h), self.n_cams, self.n_points, self.n_obs, _ptr(cams),
+                                              _ptr(points), _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), mode,
+                                              _stream()))
+            self._h = h
+            return
         nbytes = lib.caspar_ba_workspace_bytes(self.n_cams, self.n_points, self.n_obs, mode)
         if nbytes == 0:
             raise ValueError("unsupported problem size or precision")
@@ -93,7 +104,6 @@ class BundleAdjuster:
         off = (-base) % 256
         self._ws_ptr = C.c_void_p(base + off)
         self._ws_bytes = nbytes
-        h = C.c_void_p()
         check(lib.caspar_ba_create(C.byref(h), self.n_cams, self.n_points, self.n_obs, _ptr(cams), _ptr(points),
                                    _ptr(obs_cam), _ptr(obs_pt), _ptr(obs_px), mode, self._ws_ptr,
                                    self._ws_bytes, _stream()))

@@ -255,6 +255,8 @@ struct caspar_ba {
   double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
   cba::DevScalars* scal = nullptr;
   cba::DevScalars* scal_host = nullptr;  // pinned host memory the scalar read-backs land in
+  cba::DevScalars scal_local{};          // their landing place for a handle on the static workspace
+  int static_dev = -1;                   // device whose static workspace this handle holds (-1: none)
 
   // kernel timing (roofline reporting): every timing_every-th launch of the
   // fused product (counted over the launches since timing was switched on)
@@ -291,6 +293,13 @@ struct Plan {
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;
 };
 bool make_plan(int nc, int np, int64_t no, int mode, Plan& plan);
+
+// The static workspace of caspar_ba_create_static (one per device, for
+// callers that cannot allocate): its size, and the claim a handle holds on
+// the current device's copy while it lives.
+constexpr size_t kStaticWorkspaceBytes = (size_t)256 << 20;
+void* static_workspace_claim(int dev);
+void static_workspace_release(int dev);
 
 inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
 

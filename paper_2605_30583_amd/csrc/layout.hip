@@ -18,6 +18,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -665,8 +666,160 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
 
 }  // namespace cba
 
+// Static workspace for callers that cannot allocate (caspar_ba_create_static):
+// one file-scope device array, each GPU holding its own copy for the life of
+// the process.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.  One
+// handle at a time may hold a device's array; the claim is released when that
+// handle is destroyed.
+static __device__ __align__(256) unsigned char scratch[cba::kStaticWorkspaceBytes];
+
+namespace {
+std::mutex g_static_mu;
+std::vector<void*> g_static_ptr;   // per device: scratch's device address (nullptr: not looked up)
+std::vector<char> g_static_held;   // per device: held by a live handle
+}  // namespace
+
+namespace cba {
+void* static_workspace_claim(int dev) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if ((size_t)dev >= g_static_ptr.size()) {
+    g_static_ptr.resize((size_t)dev + 1, nullptr);
+    g_static_held.resize((size_t)dev + 1, 0);
+  }
+  if (g_static_held[dev])
+    fail(CASPAR_EINVAL, "the static workspace of this GPU is held by another handle (destroy it first)");
+  if (g_static_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      fail(CASPAR_EHIP, std::string("hipGetSymbolAddress of the static workspace failed: ") + hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  g_static_held[dev] = 1;
+  return g_static_ptr[dev];
+}
+
+void static_workspace_release(int dev) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (dev >= 0 && (size_t)dev < g_static_held.size()) g_static_held[dev] = 0;
+}
+}  // namespace cba
+
+namespace cba {
+
+// create() on a given workspace.  static_dev >= 0: the workspace is that
+// device's static array (no host staging buffer is allocated either; scalar
+// read-backs land in the handle itself).
+static int create_impl(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs, const double* cams,
+                       const double* points, const int32_t* obs_cam, const int32_t* obs_pt, const double* obs_px,
+                       int mode, void* workspace, size_t workspace_bytes, void* hip_stream, int static_dev) {
+  caspar_ba* h = nullptr;
+  try {
+    CBA_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    Plan plan;
+    CBA_REQUIRE(make_plan(n_cams, n_points, n_obs, mode, plan),
+                "bad sizes or mode (n_obs < 2^31, n_cams < 2^25, observations need cameras and points)");
+    if (static_dev >= 0) {
+      if (plan.total > kStaticWorkspaceBytes)
+        fail(CASPAR_ENOMEM, "problem needs " + std::to_string(plan.total) +
+                                " bytes of workspace; the static workspace holds " +
+                                std::to_string(kStaticWorkspaceBytes) + " (use caspar_ba_create)");
+      workspace = static_workspace_claim(static_dev);
+      workspace_bytes = kStaticWorkspaceBytes;
+    }
+    if (workspace_bytes < plan.total)
+      fail(CASPAR_ENOMEM, "workspace too small: need " + std::to_string(plan.total) + " bytes");
+    CBA_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+                "workspace must be non-NULL and 256-byte aligned");
+    CBA_REQUIRE(n_obs == 0 || (obs_cam && obs_pt && obs_px), "observation arrays are NULL");
+    CBA_REQUIRE(n_cams == 0 || cams, "cams is NULL");
+    CBA_REQUIRE(n_points == 0 || points, "points is NULL");
+    h = new caspar_ba();
+    h->static_dev = static_dev;
+    static_dev = -1;  // released by the handle from here on
+    h->nc = n_cams;
+    h->np = n_points;
+    h->no = (int)n_obs;
+    h->prec = mode & 1;
+    h->rj = (mode & CASPAR_RECOMPUTE_JACOBIAN) != 0;
+    h->N = 9 * n_cams + 3 * n_points;
+    h->stream = (hipStream_t)hip_stream;
+    h->no_pad = (int)align_up((size_t)n_obs, kJBlock);
+    h->K = plan.K;
+    CBA_HIP(hipGetDevice(&h->device));
+    char* ws = (char*)workspace;
+    h->scal = (DevScalars*)(ws + plan.scal.off);
+    if (h->static_dev >= 0)
+      h->scal_host = &h->scal_local;
+    else
+      CBA_HIP(hipHostMalloc((void**)&h->scal_host, sizeof(DevScalars), hipHostMallocDefault));
+    h->partials = (double*)(ws + plan.partials.off);
+    h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
+    h->cam = (double*)(ws + plan.cam.off);
+    h->cam_trial = (double*)(ws + plan.cam_trial.off);
+    h->cam_s = ws + plan.cam_s.off;
+    h->cam_trial_s = ws + plan.cam_trial_s.off;
+    h->pts_s = ws + plan.pts_s.off;
+    h->wts = ws + plan.wts.off;
+    h->X = (double*)(ws + plan.X.off);
+    h->X_trial = (double*)(ws + plan.X_trial.off);
+    h->cam_c2i = (int*)(ws + plan.cam_c2i.off);
+    h->cam_i2c = (int*)(ws + plan.cam_i2c.off);
+    h->pt_c2i = (int*)(ws + plan.pt_c2i.off);
+    h->pt_i2c = (int*)(ws + plan.pt_i2c.off);
+    h->obs_s2c = (int*)(ws + plan.obs_s2c.off);
+    h->meta = (uint32_t*)(ws + plan.meta.off);
+    h->px = (double*)(ws + plan.px.off);
+    h->J = ws + plan.J.off;
+    h->tiles = (Tile*)(ws + plan.tiles.off);
+    h->cold_lo = (int*)(ws + plan.cold_lo.off);
+    h->p_cam = ws + plan.p_cam.off;
+    h->cm_obs = (int*)(ws + plan.cm_obs.off);
+    h->cm_pt = (int*)(ws + plan.cm_pt.off);
+    h->cm_px = (double*)(ws + plan.cm_px.off);
+    h->px_s = ws + plan.px_s.off;
+    h->cm_px_s = ws + plan.cm_px_s.off;
+    h->cam_off = (int*)(ws + plan.cam_off.off);
+    h->chunks = (Chunk*)(ws + plan.chunks.off);
+    h->chunk_off = (int*)(ws + plan.chunk_off.off);
+    h->chunk_rows = (double*)(ws + plan.chunk_rows.off);
+    h->cold_list = (int*)(ws + plan.cold_list.off);
+    h->cold_off = (int*)(ws + plan.cold_off.off);
+    h->cold_rows = ws + plan.cold_rows.off;
+    h->split_pts = (SplitPoint*)(ws + plan.split_pts.off);
+    h->split_rows = (double*)(ws + plan.split_rows.off);
+    h->hot_rows = ws + plan.hot_rows.off;
+    h->Hcc = (double*)(ws + plan.Hcc.off);
+    h->Hpp = (double*)(ws + plan.Hpp.off);
+    h->Mc = ws + plan.Mc.off;
+    h->Mp = ws + plan.Mp.off;
+    void** vp[8] = {&h->vec.g, &h->vec.D, &h->vec.x, &h->vec.r, &h->vec.z, &h->vec.p, &h->vec.w, &h->vec.v};
+    for (int i = 0; i < 8; ++i) *vp[i] = ws + plan.vecs.off + i * plan.vec_bytes;
+    build_layout(h, cams, points, obs_cam, obs_pt, obs_px, ws, plan);
+    *out = h;
+  } catch (const Error& e) {
+    delete h;
+    if (static_dev >= 0) static_workspace_release(static_dev);
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::exception& e) {
+    delete h;
+    if (static_dev >= 0) static_workspace_release(static_dev);
+    set_last_error(e.what());
+    return CASPAR_EHIP;
+  }
+  set_last_error("");
+  return CASPAR_OK;
+}
+
+}  // namespace cba
+
 caspar_ba::~caspar_ba() {
-  if (scal_host) (void)hipHostFree(scal_host);
+  if (scal_host && static_dev < 0) (void)hipHostFree(scal_host);
+  if (static_dev >= 0) cba::static_workspace_release(static_dev);
   for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
 }
@@ -716,89 +869,21 @@ int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t 
                      const double* cams, const double* points, const int32_t* obs_cam,
                      const int32_t* obs_pt, const double* obs_px, int mode, void* workspace,
                      size_t workspace_bytes, void* hip_stream) {
-  caspar_ba* h = nullptr;
-  try {
-    CBA_REQUIRE(out != nullptr, "out is NULL");
-    *out = nullptr;
-    Plan plan;
-    CBA_REQUIRE(make_plan(n_cams, n_points, n_obs, mode, plan),
-                "bad sizes or mode (n_obs < 2^31, n_cams < 2^25, observations need cameras and points)");
-    if (workspace_bytes < plan.total)
-      fail(CASPAR_ENOMEM, "workspace too small: need " + std::to_string(plan.total) + " bytes");
-    CBA_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
-                "workspace must be non-NULL and 256-byte aligned");
-    CBA_REQUIRE(n_obs == 0 || (obs_cam && obs_pt && obs_px), "observation arrays are NULL");
-    CBA_REQUIRE(n_cams == 0 || cams, "cams is NULL");
-    CBA_REQUIRE(n_points == 0 || points, "points is NULL");
-    h = new caspar_ba();
-    h->nc = n_cams;
-    h->np = n_points;
-    h->no = (int)n_obs;
-    h->prec = mode & 1;
-    h->rj = (mode & CASPAR_RECOMPUTE_JACOBIAN) != 0;
-    h->N = 9 * n_cams + 3 * n_points;
-    h->stream = (hipStream_t)hip_stream;
-    h->no_pad = (int)align_up((size_t)n_obs, kJBlock);
-    h->K = plan.K;
-    CBA_HIP(hipGetDevice(&h->device));
-    char* ws = (char*)workspace;
-    h->scal = (DevScalars*)(ws + plan.scal.off);
-    CBA_HIP(hipHostMalloc((void**)&h->scal_host, sizeof(DevScalars), hipHostMallocDefault));
-    h->partials = (double*)(ws + plan.partials.off);
-    h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
-    h->cam = (double*)(ws + plan.cam.off);
-    h->cam_trial = (double*)(ws + plan.cam_trial.off);
-    h->cam_s = ws + plan.cam_s.off;
-    h->cam_trial_s = ws + plan.cam_trial_s.off;
-    h->pts_s = ws + plan.pts_s.off;
-    h->wts = ws + plan.wts.off;
-    h->X = (double*)(ws + plan.X.off);
-    h->X_trial = (double*)(ws + plan.X_trial.off);
-    h->cam_c2i = (int*)(ws + plan.cam_c2i.off);
-    h->cam_i2c = (int*)(ws + plan.cam_i2c.off);
-    h->pt_c2i = (int*)(ws + plan.pt_c2i.off);
-    h->pt_i2c = (int*)(ws + plan.pt_i2c.off);
-    h->obs_s2c = (int*)(ws + plan.obs_s2c.off);
-    h->meta = (uint32_t*)(ws + plan.meta.off);
-    h->px = (double*)(ws + plan.px.off);
-    h->J = ws + plan.J.off;
-    h->tiles = (Tile*)(ws + plan.tiles.off);
-    h->cold_lo = (int*)(ws + plan.cold_lo.off);
-    h->p_cam = ws + plan.p_cam.off;
-    h->cm_obs = (int*)(ws + plan.cm_obs.off);
-    h->cm_pt = (int*)(ws + plan.cm_pt.off);
-    h->cm_px = (double*)(ws + plan.cm_px.off);
-    h->px_s = ws + plan.px_s.off;
-    h->cm_px_s = ws + plan.cm_px_s.off;
-    h->cam_off = (int*)(ws + plan.cam_off.off);
-    h->chunks = (Chunk*)(ws + plan.chunks.off);
-    h->chunk_off = (int*)(ws + plan.chunk_off.off);
-    h->chunk_rows = (double*)(ws + plan.chunk_rows.off);
-    h->cold_list = (int*)(ws + plan.cold_list.off);
-    h->cold_off = (int*)(ws + plan.cold_off.off);
-    h->cold_rows = ws + plan.cold_rows.off;
-    h->split_pts = (SplitPoint*)(ws + plan.split_pts.off);
-    h->split_rows = (double*)(ws + plan.split_rows.off);
-    h->hot_rows = ws + plan.hot_rows.off;
-    h->Hcc = (double*)(ws + plan.Hcc.off);
-    h->Hpp = (double*)(ws + plan.Hpp.off);
-    h->Mc = ws + plan.Mc.off;
-    h->Mp = ws + plan.Mp.off;
-    void** vp[8] = {&h->vec.g, &h->vec.D, &h->vec.x, &h->vec.r, &h->vec.z, &h->vec.p, &h->vec.w, &h->vec.v};
-    for (int i = 0; i < 8; ++i) *vp[i] = ws + plan.vecs.off + i * plan.vec_bytes;
-    build_layout(h, cams, points, obs_cam, obs_pt, obs_px, ws, plan);
-    *out = h;
-  } catch (const Error& e) {
-    delete h;
-    set_last_error(e.msg);
-    return e.status;
-  } catch (const std::exception& e) {
-    delete h;
-    set_last_error(e.what());
+  return create_impl(out, n_cams, n_points, n_obs, cams, points, obs_cam, obs_pt, obs_px, mode, workspace,
+                     workspace_bytes, hip_stream, -1);
+}
+
+int caspar_ba_create_static(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                            const double* cams, const double* points, const int32_t* obs_cam,
+                            const int32_t* obs_pt, const double* obs_px, int mode, void* hip_stream) {
+  int dev = -1;
+  if (out) *out = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    set_last_error("hipGetDevice failed");
     return CASPAR_EHIP;
   }
-  set_last_error("");
-  return CASPAR_OK;
+  return create_impl(out, n_cams, n_points, n_obs, cams, points, obs_cam, obs_pt, obs_px, mode, nullptr, 0,
+                     hip_stream, dev);
 }
 
 void caspar_ba_destroy(caspar_ba* h) { delete h; }
