@@ -59,6 +59,10 @@ constexpr int kPartialWidth = 4;     // doubles per partial slot
 constexpr int kCamBits = 25;         // meta: camera id bits; local point in bits 25..30
 constexpr int kNumCUs = 256;
 constexpr int kMaxGroups = 2 * kNumCUs;  // workgroups of the fused product, at most
+// Point-per-lane product (recomputed blocks): a lane takes one point and
+// loops over its observations; points with more observations than this are
+// cut into pieces of at most this many (their sums go to split rows).
+constexpr int kLaneObsMax = 16;
 
 // Row of one cold observation outside its workgroup's window: its 9 camera
 // values in the working precision; float64 rows are padded to whole 16-byte
@@ -234,6 +238,19 @@ struct caspar_ba {
   double* win_rows = nullptr;   // [G][L][kColdRow] window sums (float64), inside the cold_rows region
   cba::SplitPoint* split_pts = nullptr;
   double* split_rows = nullptr; // [n_split_tiles][9]
+
+  // point-per-lane product (recomputed blocks): lane units in internal point
+  // order, 64 per wave tile; a unit is a whole point or a piece of at most
+  // kLaneObsMax observations of a point with more
+  int n_units = 0;
+  int n_lane_tiles = 0;
+  int n_lane_split_pts = 0;      // points cut into pieces
+  int* unit_obs = nullptr;       // [n_units + 1] first observation of each unit
+  int* unit_pt = nullptr;        // [n_units] point | piece << 31 | first piece << 30
+  int* unit_row = nullptr;       // [n_units] split row of a piece (-1 for whole points)
+  int2* lane_tiles = nullptr;    // [n_lane_tiles] (trip count, first cold row)
+  cba::SplitPoint* lane_split_pts = nullptr;
+  double* lane_split_rows = nullptr;  // [pieces][kPtRowWidth] (3 used)
   void* hot_rows = nullptr;     // [G][K][9] accumulator type
 
   // normal-equation blocks
@@ -287,10 +304,12 @@ struct Plan {
   };
   Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, px_s, cm_px_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
-      split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows;
+      split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows, unit_obs, unit_pt,
+      unit_row, lane_tiles, lane_split_pts, lane_split_rows;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;
+  size_t max_units = 0, max_lane_tiles = 0, max_pieces = 0, max_lane_split_pts = 0;
 };
 bool make_plan(int nc, int np, int64_t no, int mode, Plan& plan);
 

@@ -81,6 +81,13 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   p.max_cold = nc > p.K ? (size_t)((no * (int64_t)(nc - p.K)) / nc + 1) : 0;
   p.max_split_tiles = (size_t)no / 32 + 2;
   p.max_split_pts = (size_t)no / 65 + 1;
+  if (rj) {
+    // a point of k observations makes ceil(k / kLaneObsMax) units
+    p.max_units = (size_t)np + (size_t)no / kLaneObsMax + 1;
+    p.max_lane_tiles = p.max_units / kWave + 1;
+    p.max_pieces = (size_t)no / 8 + 2;
+    p.max_lane_split_pts = (size_t)no / (kLaneObsMax + 1) + 1;
+  }
 
   size_t off = 0;
   auto take = [&](Plan::Region& r, size_t bytes) {
@@ -142,6 +149,12 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   p.vec_bytes = align_up(std::max<size_t>(N, 1) * s);
   take(p.vecs, 8 * p.vec_bytes);
   take(p.cm_obs, (size_t)no * 4);
+  take(p.unit_obs, (p.max_units + 1) * 4);
+  take(p.unit_pt, p.max_units * 4 + 4);
+  take(p.unit_row, p.max_units * 4 + 4);
+  take(p.lane_tiles, p.max_lane_tiles * 8 + 8);
+  take(p.lane_split_pts, p.max_lane_split_pts * sizeof(SplitPoint) + 16);
+  take(p.lane_split_rows, p.max_pieces * kPtRowWidth * 8 + 8);
   p.total = off;
   return true;
 }
@@ -533,6 +546,53 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   if ((size_t)h->n_split_tiles > plan.max_split_tiles) fail(CASPAR_ENOMEM, "internal: split rows");
   h2d(h, h->split_pts, splits);
 
+  // Lane units of the point-per-lane product (recomputed blocks): whole
+  // points of at most kLaneObsMax observations, pieces of the others; 64
+  // units per wave tile, whose trip count is its largest unit.
+  std::vector<int> unit_obs, unit_pt, unit_row;
+  std::vector<int2> lane_tiles;
+  if (h->rj && no) {
+    std::vector<SplitPoint> lsplits;
+    int64_t off = 0;
+    int row = 0;
+    for (int i = n_orphan; i < np; ++i) {
+      const int k = pcnt[pt_i2c[i]];
+      if (k <= kLaneObsMax) {
+        unit_obs.push_back((int)off);
+        unit_pt.push_back(i);
+        unit_row.push_back(-1);
+      } else {
+        SplitPoint sp{i, row, 0, 0};
+        for (int s0 = 0; s0 < k; s0 += kLaneObsMax) {
+          unit_obs.push_back((int)(off + s0));
+          unit_pt.push_back((int)((unsigned)i | (1u << 31) | ((s0 == 0 ? 1u : 0u) << 30)));
+          unit_row.push_back(row++);
+          sp.nrows++;
+        }
+        lsplits.push_back(sp);
+      }
+      off += k;
+    }
+    unit_obs.push_back((int)off);
+    h->n_units = (int)unit_pt.size();
+    h->n_lane_tiles = (h->n_units + kWave - 1) / kWave;
+    h->n_lane_split_pts = (int)lsplits.size();
+    if ((size_t)h->n_units > plan.max_units || (size_t)h->n_lane_tiles > plan.max_lane_tiles ||
+        lsplits.size() > plan.max_lane_split_pts || (size_t)row > plan.max_pieces)
+      fail(CASPAR_ENOMEM, "internal: lane units exceed plan");
+    // trip counts of at least two: the product looks two iterations ahead,
+    // into this tile or the next
+    lane_tiles.assign(h->n_lane_tiles, make_int2(2, 0));
+    for (int u = 0; u < h->n_units; ++u) {
+      int2& lt = lane_tiles[u / kWave];
+      lt.x = std::max(lt.x, unit_obs[u + 1] - unit_obs[u]);
+    }
+    h2d(h, h->unit_obs, unit_obs);
+    h2d(h, h->unit_pt, unit_pt);
+    h2d(h, h->unit_row, unit_row);
+    h2d(h, h->lane_split_pts, lsplits);
+  }
+
   // Point-major sort of the observations.
   const int pt_bits = std::max(1, ceil_log2((long long)np + 1));
   const int cam_bits = std::max(1, ceil_log2((long long)nc + 1));
@@ -578,8 +638,10 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
 
   // Fused-product grid: workgroup g takes tiles [n_tiles g / G, n_tiles (g + 1) / G).
   const int waves = matvec_waves(h->prec, h->rj);
+  const bool lane_mode = h->rj;  // the product runs point-per-lane over the lane tiles
+  const int n_ptiles = lane_mode ? h->n_lane_tiles : h->n_tiles;
   h->L = nc > h->K ? std::min(kColdWin, nc - h->K) : 0;
-  h->G = std::max(1, std::min(groups_per_cu(h->K, h->L) * kNumCUs, (h->n_tiles + waves - 1) / waves));
+  h->G = std::max(1, std::min(groups_per_cu(h->K, h->L) * kNumCUs, (n_ptiles + waves - 1) / waves));
 
   // Cold cameras (internal id >= K).  Points are ordered by their least
   // observed camera, so the cold observations of one workgroup's tiles
@@ -594,17 +656,42 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   if (h->n_cold > 0) {
     std::vector<uint32_t> meta_h = d2h(h, h->meta, (size_t)no);
     const int K = h->K, L = h->L, G = h->G;
-    auto cam_of = [&](int t, int lane) { return (int)(meta_h[tiles[t].obs_begin + lane] & ((1u << kCamBits) - 1)); };
+    auto cam_at = [&](int64_t o) { return (int)(meta_h[o] & ((1u << kCamBits) - 1)); };
+    // the cameras of product tile t in the order the kernel visits them: lane
+    // order (observation per lane), or iteration-major, lane-minor with each
+    // unit's observations rotated by lane mod k (point per lane)
+    auto tile_cams = [&](int t, auto&& f) {
+      if (!lane_mode) {
+        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane) f(cam_at(tiles[t].obs_begin + lane));
+        return;
+      }
+      const int u0 = t * kWave, u1 = std::min(h->n_units, u0 + kWave);
+      for (int it = 0; it < lane_tiles[t].x; ++it)
+        for (int u = u0; u < u1; ++u) {
+          const int ob = unit_obs[u], k = unit_obs[u + 1] - ob;
+          if (it >= k) continue;
+          int j = it + (u - u0) % k;
+          if (j >= k) j -= k;
+          f(cam_at((int64_t)ob + j));
+        }
+    };
+    auto set_cold_begin = [&](int t, int v) {
+      if (lane_mode)
+        lane_tiles[t].y = v;
+      else
+        tiles[t].cold_begin = v;
+    };
     std::vector<int> lo(G, K);
     std::vector<std::vector<int>> rows_of(nc - K);
     std::vector<int> ids;
     int run = 0, n_cold_seen = 0;
     for (int g = 0; g < G; ++g) {
-      const int t0 = (int)((int64_t)h->n_tiles * g / G), t1 = (int)((int64_t)h->n_tiles * (g + 1) / G);
+      const int t0 = (int)((int64_t)n_ptiles * g / G), t1 = (int)((int64_t)n_ptiles * (g + 1) / G);
       ids.clear();
       for (int t = t0; t < t1; ++t)
-        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane)
-          if (cam_of(t, lane) >= K) ids.push_back(cam_of(t, lane));
+        tile_cams(t, [&](int c) {
+          if (c >= K) ids.push_back(c);
+        });
       std::sort(ids.begin(), ids.end());
       // window [lo, lo + L) holding the most of this workgroup's cold observations
       int best = 0;
@@ -616,13 +703,12 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
         }
       }
       for (int t = t0; t < t1; ++t) {
-        tiles[t].cold_begin = run;
-        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane) {
-          const int c = cam_of(t, lane);
-          if (c < K) continue;
+        set_cold_begin(t, run);
+        tile_cams(t, [&](int c) {
+          if (c < K) return;
           ++n_cold_seen;
           if (c < lo[g] || c >= lo[g] + L) rows_of[c - K].push_back(run++);
-        }
+        });
       }
     }
     if (n_cold_seen != h->n_cold) fail(CASPAR_EINVAL, "internal: cold count mismatch");
@@ -631,12 +717,11 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
     h->cold_local_base = run;
     for (int g = 0; g < G; ++g) {
       std::vector<char> used(L, 0);
-      const int t0 = (int)((int64_t)h->n_tiles * g / G), t1 = (int)((int64_t)h->n_tiles * (g + 1) / G);
+      const int t0 = (int)((int64_t)n_ptiles * g / G), t1 = (int)((int64_t)n_ptiles * (g + 1) / G);
       for (int t = t0; t < t1; ++t)
-        for (int lane = 0; lane < tile_nobs(tiles[t].info); ++lane) {
-          const int c = cam_of(t, lane);
+        tile_cams(t, [&](int c) {
           if (c >= K && c >= lo[g] && c < lo[g] + L) used[c - lo[g]] = 1;
-        }
+        });
       for (int sl = 0; sl < L; ++sl)
         if (used[sl]) rows_of[lo[g] + sl - K].push_back(run + g * L + sl);
     }
@@ -650,13 +735,12 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
       coff[c - K + 1] = coff[c - K] + (int)rows_of[c - K].size();
       clist.insert(clist.end(), rows_of[c - K].begin(), rows_of[c - K].end());
     }
-    h2d(h, h->tiles, tiles);
     h2d(h, h->cold_lo, lo);
     h2d(h, h->cold_off, coff);
     h2d(h, h->cold_list, clist);
-  } else if (no) {
-    h2d(h, h->tiles, tiles);
   }
+  if (no) h2d(h, h->tiles, tiles);
+  if (lane_mode) h2d(h, h->lane_tiles, lane_tiles);
 
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);
@@ -791,6 +875,12 @@ static int create_impl(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_
     h->cold_rows = ws + plan.cold_rows.off;
     h->split_pts = (SplitPoint*)(ws + plan.split_pts.off);
     h->split_rows = (double*)(ws + plan.split_rows.off);
+    h->unit_obs = (int*)(ws + plan.unit_obs.off);
+    h->unit_pt = (int*)(ws + plan.unit_pt.off);
+    h->unit_row = (int*)(ws + plan.unit_row.off);
+    h->lane_tiles = (int2*)(ws + plan.lane_tiles.off);
+    h->lane_split_pts = (SplitPoint*)(ws + plan.lane_split_pts.off);
+    h->lane_split_rows = (double*)(ws + plan.lane_split_rows.off);
     h->hot_rows = ws + plan.hot_rows.off;
     h->Hcc = (double*)(ws + plan.Hcc.off);
     h->Hpp = (double*)(ws + plan.Hpp.off);

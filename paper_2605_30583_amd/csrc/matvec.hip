@@ -423,6 +423,240 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
   for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
 }
 
+// Point-per-lane fused product (recomputed blocks).  A wave tile is 64
+// consecutive lane units: a point with at most kLaneObsMax observations, or a
+// piece of one with more.  Lane l takes unit 64 t + l, loads its point's X,
+// p and D once, and loops over the unit's observations (trip count: the
+// tile's largest unit), keeping the point sum J_p^T q in registers; the
+// observation of iteration i is (i + l) mod k: neighbouring lanes take
+// different ranks of their points' camera lists (each sorted by camera),
+// so the lanes of one LDS access that hit the same camera (the most observed
+// one, or the tile's shared least observed one) are spread over the wave.  Camera sums go to LDS
+// (hot cameras, the window) or to cold rows exactly as in k_matvec, the rows
+// numbered per tile in (iteration, lane) order.  A whole point writes its row
+// of w directly (64 consecutive points per tile: coalesced); a piece writes a
+// split row that k_matvec_final adds up.
+template <typename S>
+__global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
+    int n_tiles, int G, const int2* __restrict__ ltiles, int n_units, const int* __restrict__ unit_obs,
+    const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const uint32_t* __restrict__ meta,
+    const S* __restrict__ pts_s, const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
+    const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
+    int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
+    double* __restrict__ split_rows, double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L,
+    unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
+  constexpr int THREADS = MvCfg<S, true>::threads;
+  constexpr int WAVES = THREADS / kWave;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
+  double* priv = hot + (size_t)K * 9;                      // [kPrivCopies][P][9]
+  double* win = priv + (size_t)kPrivCopies * P * 9;        // [L][9]
+  const int lo = L > 0 ? cold_lo[blockIdx.x] : 0;
+  __shared__ double red[WAVES];
+  if (sc != nullptr && sc->done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->last_x = 0;
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  for (int i = tid; i < (K + kPrivCopies * P + L) * 9; i += THREADS) hot[i] = 0.0;
+  __syncthreads();
+
+  const S* __restrict__ pp_base = p + 9 * (size_t)nc;
+  const S* __restrict__ dp_base = D + 9 * (size_t)nc;
+  S* __restrict__ wp_base = w + 9 * (size_t)nc;
+  const __amdgpu_buffer_rsrc_t w_rs = buffer_of(wp_base, w_pt_bytes);
+  const __amdgpu_buffer_rsrc_t cold_rs = buffer_of(cold_rows, cold_bytes);
+  const uint32_t cmask = (1u << kCamBits) - 1u;
+  double pap = 0.0;
+  const int t0 = (int)((int64_t)n_tiles * blockIdx.x / G);
+  const int t1 = (int)((int64_t)n_tiles * (blockIdx.x + 1) / G);
+
+  // Software pipeline over the wave's steps (tile t, iteration i), tiles
+  // t, t + W, t + 2W, ... (W waves), every tile at least two iterations long:
+  //   step s         computed: its camera row (and IRLS weight) in registers;
+  //   step s + 1     camera row requested during step s, from its meta word;
+  //   step s + 2     meta word requested during step s.
+  // Steps s + 1 and s + 2 lie in the current tile or the next one, so the
+  // unit data (first observation, count, point) are kept for this tile and the
+  // next two, and the point data (X, p, D) for this tile and the next.
+  int t = t0 + __builtin_amdgcn_readfirstlane(wv);
+  if (t < t1) {
+    struct Unit {
+      int ob, k, rot;
+      unsigned ptw;
+    };
+    // lanes of a tile past the range (or past the last unit) get k = 0 and
+    // in-range addresses
+    auto unit_at = [&](int tt) {
+      Unit U;
+      const int u = tt * kWave + lane;
+      const bool valid = tt < t1 && u < n_units;
+      const int uc = valid ? u : n_units - 1;
+      U.ob = unit_obs[uc];
+      U.k = valid ? unit_obs[uc + 1] - U.ob : 0;
+      U.ptw = valid ? (unsigned)unit_pt[uc] : 0u;
+      U.rot = U.k > 0 ? lane % U.k : 0;
+      return U;
+    };
+    auto obs_of = [&](const Unit& U, int i) {
+      int j = i + U.rot;
+      if (j >= U.k) j -= U.k;
+      return i < U.k ? U.ob + j : U.ob;
+    };
+    struct Pt {
+      S x[3], p[3], d[3];
+    };
+    auto point_of = [&](const Unit& U) {
+      Pt P;
+      const int pt = (int)(U.ptw & 0x3fffffffu);
+      load_point<S>(pts_s, (size_t)pt, P.x);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        P.p[q] = pp_base[3 * (size_t)pt + q];
+        P.d[q] = dp_base[3 * (size_t)pt + q];
+      }
+      return P;
+    };
+    auto tile_info = [&](int tt) { return ltiles[min(tt, n_tiles - 1)]; };
+
+    Unit Uc = unit_at(t), Un = unit_at(t + WAVES), Unn = unit_at(t + 2 * WAVES);
+    int2 ti_c = tile_info(t), ti_n = tile_info(t + WAVES);
+    Pt Pc = point_of(Uc), Pn = point_of(Un);
+    int it = 0;
+    int cold_row = ti_c.y;
+    S acc[3] = {(S)0, (S)0, (S)0};
+    // step s (current), s + 1 and their observations; meta of s + 1
+    int o_c = obs_of(Uc, 0);
+    int o_1 = obs_of(Uc, 1);  // trip >= 2
+    uint32_t m_1 = meta[o_1];
+    struct Row {
+      S c[kProdCamRow];
+      S wgt;
+      int cid;  // the camera
+    };
+    Row RA, RB;
+    {
+      const uint32_t m0 = meta[o_c];
+      load_prod_cam<S>(p_cam, (int)(m0 & cmask), RA.c);
+      RA.wgt = wts != nullptr ? wts[o_c] : (S)1;
+      RA.cid = (int)(m0 & cmask);
+    }
+
+    // One step: compute step s from cur while step s + 1's row comes into
+    // nxt.  Returns true after the wave's last step.
+    auto step = [&](Row& cur, Row& nxt) -> bool {
+      // the step after next: this tile or the next
+      const bool in_tile2 = it + 2 < ti_c.x;
+      const int o_2 = in_tile2 ? obs_of(Uc, it + 2) : obs_of(Un, it + 2 - ti_c.x);
+      __builtin_amdgcn_sched_barrier(0);
+      // requests: the row of step s + 1, the meta word of step s + 2
+      load_prod_cam<S>(p_cam, (int)(m_1 & cmask), nxt.c);
+      nxt.wgt = wts != nullptr ? wts[o_1] : (S)1;
+      nxt.cid = (int)(m_1 & cmask);
+      const uint32_t m_2 = meta[o_2];
+      __builtin_amdgcn_sched_barrier(0);
+      // step s
+      const bool act = it < Uc.k;
+      const int ci_raw = cur.cid;
+      S yc[9], yp[3];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) yc[q] = (S)0;
+      const int ci = act ? ci_raw : -1;
+      if (act) {
+        const Cam<S> cam = prod_cam<S>(cur.c);
+        const S* pc = cur.c + kProdCamP;
+        const S qwq = wts != nullptr
+                          ? snavely_apply<true, S>(cam, Pc.x[0], Pc.x[1], Pc.x[2], pc, Pc.p, cur.wgt, yc, yp)
+                          : snavely_apply<false, S>(cam, Pc.x[0], Pc.x[1], Pc.x[2], pc, Pc.p, (S)1, yc, yp);
+        pap += (double)qwq;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[q] += yp[q];
+        const unsigned slot = (unsigned)(ci - lo);
+        if (ci < K || slot < (unsigned)L) {
+          double* a = ci < P ? priv + ((size_t)(lane % kPrivCopies) * P + ci) * 9
+                             : (ci < K ? hot + 9 * ci : win + 9 * slot);
+#pragma unroll
+          for (int q = 0; q < 9; ++q) atomicAdd(a + q, (double)yc[q]);
+        }
+      }
+      // cold cameras outside the window: rows in (iteration, lane) order
+      const bool scat = act && ci >= K && (unsigned)(ci - lo) >= (unsigned)L;
+      const unsigned long long sm = __ballot(scat);
+      {
+        const unsigned row = (unsigned)cold_row + (unsigned)__popcll(sm & ((1ull << lane) - 1ull));
+        store_cold_row(cold_rs, scat ? row * (unsigned)(ColdRow<S>::n * sizeof(S)) : kDropOffset, yc);
+      }
+      cold_row += (int)__popcll(sm);
+      // advance
+      o_1 = o_2;
+      m_1 = m_2;
+      if (++it < ti_c.x) return false;
+      // end of the tile: the point's row of w (whole points) or its split row
+      {
+        const bool valid = Uc.k > 0;
+        const bool piece = (Uc.ptw >> 31) != 0u;
+        const bool first = ((Uc.ptw >> 30) & 1u) != 0u;
+        const int pt = (int)(Uc.ptw & 0x3fffffffu);
+        S dpp = (S)0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dpp = fma(Pc.d[q] * Pc.p[q], Pc.p[q], dpp);
+        if (valid && (!piece || first)) pap = fma(lambda, (double)dpp, pap);
+        if (valid && piece) {
+          double* row = split_rows + (size_t)unit_row[t * kWave + lane] * kPtRowWidth;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) row[q] = (double)acc[q];
+        }
+        S wv3[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) wv3[q] = fma((S)lambda * Pc.d[q], Pc.p[q], acc[q]);
+        store3(w_rs, valid && !piece ? (unsigned)(3 * pt) * (unsigned)sizeof(S) : kDropOffset, wv3);
+      }
+      t += WAVES;
+      if (t >= t1) return true;
+      it = 0;
+      Uc = Un;
+      Un = Unn;
+      Unn = unit_at(t + 2 * WAVES);
+      Pc = Pn;
+      Pn = point_of(Un);
+      ti_c = ti_n;
+      ti_n = tile_info(t + WAVES);
+      cold_row = ti_c.y;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[q] = (S)0;
+      return false;
+    };
+    for (;;) {
+      if (step(RA, RB)) break;
+      if (step(RB, RA)) break;
+    }
+  }
+  // lambda p^T D p of the camera blocks and of points without observations
+  for (int i = blockIdx.x * THREADS + tid; i < 9 * nc; i += G * THREADS) {
+    const double v = p[i];
+    pap = fma(lambda * (double)D[i] * v, v, pap);
+  }
+  for (int i = blockIdx.x * THREADS + tid; i < 3 * n_orphan; i += G * THREADS) {
+    const double v = pp_base[i];
+    pap = fma(lambda * (double)dp_base[i] * v, v, pap);
+  }
+  const double tot = block_sum(pap, red);  // (also orders the LDS updates before the fold)
+  if (tid == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
+  for (int i = tid; i < P * 9; i += THREADS) {
+    double s2 = hot[i];
+#pragma unroll
+    for (int c = 0; c < kPrivCopies; ++c) s2 += priv[(size_t)c * P * 9 + i];
+    hot[i] = s2;
+  }
+  __syncthreads();
+  double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
+  for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
+  double* wdst = win_rows + (size_t)blockIdx.x * L * kColdRow;
+  for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
+}
+
 // Camera rows of w, split and orphan points, p^T A p and (in PCG) alpha.
 // Block roles by index:
 //   [0, nb_hot):           column sums of the per-workgroup rows of the LDS
@@ -545,6 +779,8 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = matvec_lds_bytes(h->K, h->L);
   auto kern = k_matvec<S, RJ>;
+  // recomputed blocks run the point-per-lane kernel
+  const void* kptr = RJ ? (const void*)k_matvec_lanes<S> : (const void*)kern;
   // the dynamic-LDS limit belongs to the kernel on a device: raised only when
   // a launch needs more than it was last set to (not at every launch)
   {
@@ -553,7 +789,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
     std::lock_guard<std::mutex> lock(mu);
     if ((size_t)h->device >= lds_set.size()) lds_set.resize((size_t)h->device + 1, 65536);
     if (lds > lds_set[h->device]) {
-      CBA_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      CBA_HIP(hipFuncSetAttribute(kptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       lds_set[h->device] = lds;
     }
   }
@@ -561,6 +797,17 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   // between the kernels)
   hipEvent_t e0, e1;
   timing_events(h, &e0, &e1);
+  if constexpr (RJ) {
+    hipExtLaunchKernelGGL(k_matvec_lanes<S>, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u,
+                          h->n_lane_tiles, h->G, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt, h->unit_row,
+                          h->meta, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D,
+                          lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows,
+                          h->win_rows, h->lane_split_rows, h->partials, scp, P, h->L,
+                          (unsigned)(3 * (size_t)h->np * sizeof(S)),
+                          (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)), weights_of<S>(h));
+    CBA_LAUNCHED();
+    return;
+  }
   hipExtLaunchKernelGGL(kern, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u, h->n_tiles, h->G, h->tiles,
                         h->meta, h->J, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p,
                         (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows,
@@ -591,14 +838,16 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   const int n_partials = h->G + (h->n_between > 0 ? (int)between_grid(h) : 0);
   const int nb_hot = (h->K * 9 + kHotCols - 1) / kHotCols;
   const int nb_cold = (h->nc - h->K + 3) / 4;
-  const int64_t nrest = 3 * (int64_t)h->n_split_pts + 3 * (int64_t)h->n_orphan_pts;
+  const int64_t nrest = 3 * (int64_t)(h->rj ? h->n_lane_split_pts : h->n_split_pts) + 3 * (int64_t)h->n_orphan_pts;
   const int nb_rest = (int)((nrest + 255) / 256);
   const unsigned grid = (unsigned)std::max(1, nb_hot + nb_cold + nb_rest);
   k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, (const double*)h->hot_rows,
                                           (const S*)h->cold_rows, h->win_rows, h->cold_local_base, h->cold_off,
                                           h->cold_list, p,
-                                          (const S*)h->vec.D, lambda, w, h->n_split_pts, h->split_pts,
-                                          h->split_rows, h->n_orphan_pts, h->partials, h->scal, pcg_mode ? 1 : 0,
+                                          (const S*)h->vec.D, lambda, w, h->rj ? h->n_lane_split_pts : h->n_split_pts,
+                                          h->rj ? h->lane_split_pts : h->split_pts,
+                                          h->rj ? h->lane_split_rows : h->split_rows, h->n_orphan_pts, h->partials,
+                                          h->scal, pcg_mode ? 1 : 0,
                                           nb_hot, nb_cold, h->n_between > 0 ? h->bt_rows : nullptr, n_partials);
   CBA_LAUNCHED();
 }
