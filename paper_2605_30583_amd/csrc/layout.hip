@@ -81,13 +81,11 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   p.max_cold = nc > p.K ? (size_t)((no * (int64_t)(nc - p.K)) / nc + 1) : 0;
   p.max_split_tiles = (size_t)no / 32 + 2;
   p.max_split_pts = (size_t)no / 65 + 1;
-  if (rj) {
-    // a point of k observations makes ceil(k / kLaneObsMax) units
-    p.max_units = (size_t)np + (size_t)no / kLaneObsMax + 1;
-    p.max_lane_tiles = p.max_units / kWave + 1;
-    p.max_pieces = (size_t)no / 8 + 2;
-    p.max_lane_split_pts = (size_t)no / (kLaneObsMax + 1) + 1;
-  }
+  // lane units: a point of k observations makes ceil(k / kLaneObsMax)
+  p.max_units = (size_t)np + (size_t)no / kLaneObsMax + 1;
+  p.max_lane_tiles = p.max_units / kWave + 1;
+  p.max_pieces = (size_t)no / 8 + 2;
+  p.max_lane_split_pts = (size_t)no / (kLaneObsMax + 1) + 1;
 
   size_t off = 0;
   auto take = [&](Plan::Region& r, size_t bytes) {
@@ -546,12 +544,13 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   if ((size_t)h->n_split_tiles > plan.max_split_tiles) fail(CASPAR_ENOMEM, "internal: split rows");
   h2d(h, h->split_pts, splits);
 
-  // Lane units of the point-per-lane product (recomputed blocks): whole
-  // points of at most kLaneObsMax observations, pieces of the others; 64
-  // units per wave tile, whose trip count is its largest unit.
+  // Lane units of the point-per-lane kernels (the linearisation, and the
+  // product with recomputed blocks): whole points of at most kLaneObsMax
+  // observations, pieces of the others; 64 units per wave tile, whose trip
+  // count is its largest unit.
   std::vector<int> unit_obs, unit_pt, unit_row;
   std::vector<int2> lane_tiles;
-  if (h->rj && no) {
+  if (no) {
     std::vector<SplitPoint> lsplits;
     int64_t off = 0;
     int row = 0;
@@ -740,7 +739,7 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
     h2d(h, h->cold_list, clist);
   }
   if (no) h2d(h, h->tiles, tiles);
-  if (lane_mode) h2d(h, h->lane_tiles, lane_tiles);
+  h2d(h, h->lane_tiles, lane_tiles);
 
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);

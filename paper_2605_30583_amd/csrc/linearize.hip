@@ -204,7 +204,118 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
 }
 
-// Points with more than 64 observations: sum their tiles' rows.
+// Point side of the linearisation with recomputed blocks, one lane per lane
+// unit (a point, or a piece of at most kLaneObsMax observations of a point
+// with more): the lane loops over its observations (the tile's trip count),
+// evaluates residual and blocks, and keeps g_p and the upper triangle of H_p
+// in registers; whole points write their rows directly, pieces a split row
+// that k_lin_split adds up.  The camera row and pixel of the next
+// observation are requested before the current one is evaluated, from a
+// meta word requested one step earlier still.  (With stored blocks the
+// observation-per-lane kernel k_lin_points writes them coalesced instead.)
+template <typename S>
+__global__ __launch_bounds__(256) void k_lin_lanes(int n_tiles, const int2* __restrict__ ltiles, int n_units,
+                                                   const int* __restrict__ unit_obs, const int* __restrict__ unit_pt,
+                                                   const int* __restrict__ unit_row, const uint32_t* __restrict__ meta,
+                                                   const S* __restrict__ px, const S* __restrict__ camtab,
+                                                   const S* __restrict__ pts, S* __restrict__ g, S* __restrict__ D,
+                                                   double* __restrict__ Hpp, double* __restrict__ split_rows, int nc,
+                                                   double* __restrict__ partials, int loss, double loss_c,
+                                                   S* __restrict__ wts) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t cmask = (1u << kCamBits) - 1u;
+  using P2 = typename Pair<S>::type;
+  double cost = 0.0;
+  for (int t = blockIdx.x * 4 + wv; t < n_tiles; t += gridDim.x * 4) {
+    const int trip = ltiles[t].x;
+    const int u = t * kWave + lane;
+    const bool valid = u < n_units;
+    const int uc = valid ? u : n_units - 1;
+    const int ob = unit_obs[uc];
+    const int k = valid ? unit_obs[uc + 1] - ob : 0;
+    const unsigned ptw = (unsigned)unit_pt[uc];
+    const int pt = (int)(ptw & 0x3fffffffu);
+    // observation of step i (any of the unit's when the lane has none left)
+    auto obs = [&](int i) { return i < k ? ob + i : ob; };
+    S Xp[3];
+    load_point<S>(pts, (size_t)pt, Xp);
+    double v[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v[a] = 0.0;
+    Cam<S> c = load_cam_s<S>(camtab, (int)(meta[ob] & cmask));
+    P2 q = reinterpret_cast<const P2*>(px)[ob];
+    uint32_t m1 = meta[obs(1)];
+    for (int it = 0; it < trip; ++it) {
+      const bool act = it < k;
+      const int o = obs(it);
+      // requests: the next observation's camera row and pixel, the meta word
+      // of the one after
+      const Cam<S> cn = load_cam_s<S>(camtab, (int)(m1 & cmask));
+      const P2 qn = reinterpret_cast<const P2*>(px)[obs(it + 1)];
+      const uint32_t m2 = meta[obs(it + 2)];
+      if (act) {
+        S r0, r1, col[12][2];
+        snavely_jacobian<S>(c, Xp[0], Xp[1], Xp[2], (S)q.x, (S)q.y, r0, r1, col);
+        if (loss == CASPAR_LOSS_TRIVIAL) {
+          cost = fma((double)r0, (double)r0, fma((double)r1, (double)r1, cost));
+        } else {
+          // robust loss: cost rho(s); residual and blocks scaled by sqrt(rho'(s))
+          double w;
+          cost += robust_rho(loss, loss_c, fma((double)r0, (double)r0, (double)r1 * (double)r1), w);
+          const S sw = (S)sqrt(w);
+          r0 *= sw;
+          r1 *= sw;
+#pragma unroll
+          for (int j = 9; j < 12; ++j) {
+            col[j][0] *= sw;
+            col[j][1] *= sw;
+          }
+          wts[o] = (S)w;
+        }
+        double jp[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          jp[a][0] = col[9 + a][0];
+          jp[a][1] = col[9 + a][1];
+          v[a] = fma(jp[a][0], (double)r0, fma(jp[a][1], (double)r1, v[a]));
+        }
+        v[3] = fma(jp[0][0], jp[0][0], fma(jp[0][1], jp[0][1], v[3]));
+        v[4] = fma(jp[0][0], jp[1][0], fma(jp[0][1], jp[1][1], v[4]));
+        v[5] = fma(jp[0][0], jp[2][0], fma(jp[0][1], jp[2][1], v[5]));
+        v[6] = fma(jp[1][0], jp[1][0], fma(jp[1][1], jp[1][1], v[6]));
+        v[7] = fma(jp[1][0], jp[2][0], fma(jp[1][1], jp[2][1], v[7]));
+        v[8] = fma(jp[2][0], jp[2][0], fma(jp[2][1], jp[2][1], v[8]));
+      }
+      c = cn;
+      q = qn;
+      m1 = m2;
+    }
+    if (valid) {
+      if ((ptw >> 31) != 0u) {
+        double* row = split_rows + (size_t)unit_row[u] * kPtRowWidth;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) row[a] = v[a];
+      } else {
+        const size_t b = 9 * (size_t)nc + 3 * (size_t)pt;
+        g[b] = (S)v[0];
+        g[b + 1] = (S)v[1];
+        g[b + 2] = (S)v[2];
+        double* H = Hpp + 6 * (size_t)pt;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) H[a] = v[3 + a];
+        D[b] = (S)clamp_diag(v[3]);
+        D[b + 1] = (S)clamp_diag(v[6]);
+        D[b + 2] = (S)clamp_diag(v[8]);
+      }
+    }
+  }
+  const double tot = block_sum(cost, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kPartialWidth] = tot;
+}
+
+// Points cut into pieces: sum their pieces' rows.
 template <typename S>
 __global__ void k_lin_split(int n_split, const SplitPoint* __restrict__ sp,
                             const double* __restrict__ split_rows, S* g, S* D, double* Hpp, int nc) {
@@ -554,7 +665,7 @@ static void linearize_t(caspar_ba* h) {
   hipStream_t st = h->stream;
   S* g = (S*)h->vec.g;
   S* D = (S*)h->vec.D;
-  const unsigned tg = h->rj ? tile_grid<k_lin_points<S, false>>(h->n_tiles) : tile_grid<k_lin_points<S, true>>(h->n_tiles);
+  const unsigned tg = h->rj ? tile_grid<k_lin_lanes<S>>(h->n_lane_tiles) : tile_grid<k_lin_points<S, true>>(h->n_tiles);
   // camera rows in the working precision (float32 rows feed the point side
   // and the products; float64 reads the master rows unless the products
   // recompute their blocks)
@@ -574,24 +685,26 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   const S* ptab = (const S*)pts_table(h);
-  if (h->n_tiles > 0) {
+  if (h->rj ? h->n_lane_tiles > 0 : h->n_tiles > 0) {
     if (h->rj)
-      k_lin_points<S, false><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<S>(h), camtab, ptab, h->J, g, D,
-                                                 h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
-                                                 (S*)h->wts);
+      k_lin_lanes<S><<<tg, 256, 0, st>>>(h->n_lane_tiles, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt,
+                                         h->unit_row, h->meta, pixels_of<S>(h), camtab, ptab, g, D, h->Hpp,
+                                         h->lane_split_rows, h->nc, h->partials, h->loss, h->loss_c, (S*)h->wts);
     else
       k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<S>(h), camtab, ptab, h->J, g, D,
                                                 h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
-                                                 (S*)h->wts);
+                                                (S*)h->wts);
     CBA_LAUNCHED();
     k_sum_partials<<<1, 1024, 0, st>>>((int)tg, h->partials, 0, h->scal, 0);
     CBA_LAUNCHED();
   } else {
     CBA_HIP(hipMemsetAsync(h->scal->red, 0, sizeof(double), st));
   }
-  if (h->n_split_pts > 0) {
-    k_lin_split<S><<<nblk(h->n_split_pts, 256), 256, 0, st>>>(h->n_split_pts, h->split_pts, h->split_rows,
-                                                              g, D, h->Hpp, h->nc);
+  const int n_split = h->rj ? h->n_lane_split_pts : h->n_split_pts;
+  if (n_split > 0) {
+    k_lin_split<S><<<nblk(n_split, 256), 256, 0, st>>>(n_split, h->rj ? h->lane_split_pts : h->split_pts,
+                                                       h->rj ? h->lane_split_rows : h->split_rows, g, D, h->Hpp,
+                                                       h->nc);
     CBA_LAUNCHED();
   }
   if (h->n_orphan_pts > 0) {
