@@ -251,7 +251,7 @@ struct caspar_ba {
   int2* lane_tiles = nullptr;    // [n_lane_tiles] (trip count, first cold row)
   cba::SplitPoint* lane_split_pts = nullptr;
   double* lane_split_rows = nullptr;  // [pieces][kPtRowWidth] (3 used)
-  void* hot_rows = nullptr;     // [G][K][9] accumulator type
+  void* hot_rows = nullptr;     // [G][K][9] per-workgroup hot-camera sums, working precision
 
   // normal-equation blocks
   double* Hcc = nullptr;        // [nc][45]
@@ -363,9 +363,6 @@ inline const void* pts_table(const caspar_ba* h) {
   return h->prec == CASPAR_FP64 ? static_cast<const void*>(h->X) : h->pts_s;
 }
 
-// The fused product accumulates camera sums in float64 in both precisions
-// (ds_add_f64 in LDS measured faster than ds_add_f32 on this chip).
-inline size_t acc_bytes(int) { return 8; }
 
 // LDS of one fused-product workgroup: float64 sums of the K hot cameras,
 // kPrivCopies private copies of the most observed ones, and the L cameras of

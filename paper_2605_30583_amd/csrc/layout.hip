@@ -139,7 +139,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
     take(p.cold_rows, 256);
   take(p.split_pts, p.max_split_pts * sizeof(SplitPoint));
   take(p.split_rows, p.max_split_tiles * kPtRowWidth * 8);
-  take(p.hot_rows, (size_t)p.G * p.K * 9 * acc_bytes(prec));
+  take(p.hot_rows, (size_t)p.G * p.K * 9 * scalar_bytes(prec));
   take(p.Hcc, (size_t)nc * 45 * 8);
   take(p.Hpp, (size_t)np * 6 * 8);
   take(p.Mc, (size_t)nc * 45 * s);

@@ -163,7 +163,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     const void* __restrict__ J, const S* __restrict__ pts_s,
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
-    int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
+    int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows,
     double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L, int local_base,
     unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
@@ -417,8 +417,10 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     hot[i] = s;
   }
   __syncthreads();
-  double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
-  for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
+  // the workgroup's hot-camera sums, rounded to the working precision (the
+  // products are float32 in the mixed form; the sum over workgroups is float64)
+  S* dst = hot_rows + (size_t)blockIdx.x * K * 9;
+  for (int i = tid; i < K * 9; i += THREADS) dst[i] = (S)hot[i];
   double* wdst = win_rows + (size_t)blockIdx.x * L * kColdRow;
   for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
 }
@@ -442,7 +444,7 @@ __global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
     const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const uint32_t* __restrict__ meta,
     const S* __restrict__ pts_s, const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
-    int n_orphan, double* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
+    int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows, double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L,
     unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
   constexpr int THREADS = MvCfg<S, true>::threads;
@@ -651,8 +653,10 @@ __global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
     hot[i] = s2;
   }
   __syncthreads();
-  double* dst = hot_rows + (size_t)blockIdx.x * K * 9;
-  for (int i = tid; i < K * 9; i += THREADS) dst[i] = hot[i];
+  // the workgroup's hot-camera sums, rounded to the working precision (the
+  // products are float32 in the mixed form; the sum over workgroups is float64)
+  S* dst = hot_rows + (size_t)blockIdx.x * K * 9;
+  for (int i = tid; i < K * 9; i += THREADS) dst[i] = (S)hot[i];
   double* wdst = win_rows + (size_t)blockIdx.x * L * kColdRow;
   for (int i = tid; i < L * 9; i += THREADS) wdst[(size_t)(i / 9) * kColdRow + i % 9] = win[i];
 }
@@ -665,11 +669,14 @@ __global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
 //                          observation rows;
 //   the rest:              split points and points without observations.
 // Block 0 also turns the p^T A p partials into pAp (and alpha in PCG).
-constexpr int kHotCols = 16;  // hot-sum columns per final-kernel workgroup
+// hot-sum columns per final-kernel workgroup: one 128-byte line of each
+// workgroup row, 256 threads = kHotCols columns x (256 / kHotCols) row groups
+template <typename S>
+constexpr int kHotCols = 128 / (int)sizeof(S);
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_matvec_final(
-    int nc, int K, int G, const double* __restrict__ hot_rows,
+    int nc, int K, int G, const S* __restrict__ hot_rows,
     const S* __restrict__ cold_rows, const double* __restrict__ win_rows, int local_base,
     const int* __restrict__ cold_off,
     const int* __restrict__ cold_list, const S* __restrict__ p, const S* __restrict__ D, double lambda,
@@ -686,29 +693,30 @@ __global__ __launch_bounds__(256) void k_matvec_final(
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
   const int b = blockIdx.x;
   if (b < nb_hot) {
-    // kHotCols consecutive columns (one 128-byte line per row) x 16 row
-    // groups; each thread sums every 16th workgroup row with two independent
-    // accumulators, then the 16 group sums are added in LDS
-    double (*gsum)[kHotCols] = reinterpret_cast<double (*)[kHotCols]>(&red[0][0]);
+    // HC consecutive columns (one 128-byte line per row) x RG row groups;
+    // each thread sums every RG-th workgroup row with two independent
+    // accumulators, then the RG group sums are added in LDS
+    constexpr int HC = kHotCols<S>, RG = 256 / HC;
+    double (*gsum)[HC] = reinterpret_cast<double (*)[HC]>(&red[0][0]);
     const int ncol = K * 9;
-    const int cl = tid % kHotCols, gr = tid / kHotCols;
-    const int col = b * kHotCols + cl;
+    const int cl = tid % HC, gr = tid / HC;
+    const int col = b * HC + cl;
     double s0 = 0.0, s1 = 0.0;
     if (col < ncol) {
-      const double* r = hot_rows + col;
+      const S* r = hot_rows + col;
       int g = gr;
-      for (; g + 16 < G; g += 32) {
-        s0 += r[(size_t)g * ncol];
-        s1 += r[(size_t)(g + 16) * ncol];
+      for (; g + RG < G; g += 2 * RG) {
+        s0 += (double)r[(size_t)g * ncol];
+        s1 += (double)r[(size_t)(g + RG) * ncol];
       }
-      if (g < G) s0 += r[(size_t)g * ncol];
+      if (g < G) s0 += (double)r[(size_t)g * ncol];
     }
     gsum[gr][cl] = s0 + s1;
     __syncthreads();
     if (gr == 0 && col < ncol) {
       double tot = 0.0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) tot += gsum[k][cl];
+      for (int k = 0; k < RG; ++k) tot += gsum[k][cl];
       w[col] = (S)fma(lambda * (double)D[col], (double)p[col], tot + between_part(col));
     }
   } else if (b < nb_hot + nb_cold) {
@@ -801,7 +809,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
     hipExtLaunchKernelGGL(k_matvec_lanes<S>, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u,
                           h->n_lane_tiles, h->G, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt, h->unit_row,
                           h->meta, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D,
-                          lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows, (S*)h->cold_rows,
+                          lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows, (S*)h->cold_rows,
                           h->win_rows, h->lane_split_rows, h->partials, scp, P, h->L,
                           (unsigned)(3 * (size_t)h->np * sizeof(S)),
                           (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)), weights_of<S>(h));
@@ -810,7 +818,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   }
   hipExtLaunchKernelGGL(kern, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u, h->n_tiles, h->G, h->tiles,
                         h->meta, h->J, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p,
-                        (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (double*)h->hot_rows,
+                        (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows,
                         (S*)h->cold_rows, h->win_rows, h->split_rows, h->partials, scp, P, h->L,
                         h->cold_local_base, (unsigned)(3 * (size_t)h->np * sizeof(S)),
                         (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)),
@@ -836,12 +844,12 @@ static void matvec_t(caspar_ba* h, double lambda, const S* p, S* w, bool pcg_mod
   // pose between-factors: their share of the camera rows and of p^T A p
   run_between_product(h, p, pcg_mode);
   const int n_partials = h->G + (h->n_between > 0 ? (int)between_grid(h) : 0);
-  const int nb_hot = (h->K * 9 + kHotCols - 1) / kHotCols;
+  const int nb_hot = (h->K * 9 + kHotCols<S> - 1) / kHotCols<S>;
   const int nb_cold = (h->nc - h->K + 3) / 4;
   const int64_t nrest = 3 * (int64_t)(h->rj ? h->n_lane_split_pts : h->n_split_pts) + 3 * (int64_t)h->n_orphan_pts;
   const int nb_rest = (int)((nrest + 255) / 256);
   const unsigned grid = (unsigned)std::max(1, nb_hot + nb_cold + nb_rest);
-  k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, (const double*)h->hot_rows,
+  k_matvec_final<S><<<grid, 256, 0, st>>>(h->nc, h->K, h->G, (const S*)h->hot_rows,
                                           (const S*)h->cold_rows, h->win_rows, h->cold_local_base, h->cold_off,
                                           h->cold_list, p,
                                           (const S*)h->vec.D, lambda, w, h->rj ? h->n_lane_split_pts : h->n_split_pts,
