@@ -272,6 +272,13 @@ struct caspar_ba {
   double* gauge_rows = nullptr; // [256][35] gauge-projection partial sums
   cba::DevScalars* scal = nullptr;
   cba::DevScalars* scal_host = nullptr;  // pinned host memory the scalar read-backs land in
+  // Mapped (coherent) read-back: a kernel stores the scalars into scal_host
+  // and then publishes scal_seq at *scal_flag; the host polls the flag
+  // instead of waiting for a copy engine and a stream synchronisation.
+  // Null for a handle on the static workspace (which allocates nothing).
+  unsigned* scal_flag = nullptr;
+  char* scal_mapped_dev = nullptr;  // the device's address of the pinned block (struct, then flag)
+  unsigned scal_seq = 0;
   cba::DevScalars scal_local{};          // their landing place for a handle on the static workspace
   int static_dev = -1;                   // device whose static workspace this handle holds (-1: none)
 

@@ -368,12 +368,51 @@ static void cast_pixels(caspar_ba* h) {
 
 void sync(caspar_ba* h) { CBA_HIP(hipStreamSynchronize(h->stream)); }
 
-// A copy into pinned memory goes straight to the host; into pageable memory
-// it would be staged through a runtime buffer, a longer round trip.
+// One wave stores the scalars into mapped host memory (one 32-bit word per
+// lane), waits for its stores to reach system scope, then lane 0 publishes
+// seq.  A host that sees seq therefore sees the whole struct, and since the
+// stream runs in order, every kernel enqueued before this one has finished.
+__global__ __launch_bounds__(64) void k_scalars_out(const DevScalars* __restrict__ s, DevScalars* host,
+                                                    unsigned* flag, unsigned seq) {
+  constexpr int kWords = (int)(sizeof(DevScalars) / 4);
+  static_assert(kWords <= 64, "one word per lane");
+  const int t = threadIdx.x;
+  if (t < kWords) reinterpret_cast<volatile unsigned*>(host)[t] = reinterpret_cast<const unsigned*>(s)[t];
+  __threadfence_system();
+  if (t == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The mapped read-back costs one small kernel and a poll of host memory; a
+// copy-engine transfer plus a stream synchronisation costs tens of
+// microseconds more, several times per Levenberg-Marquardt iteration.  A
+// handle on the static workspace has no pinned memory and copies into its
+// own struct instead.
 DevScalars read_scalars(caspar_ba* h) {
-  CBA_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
-  sync(h);
-  return *h->scal_host;
+  if (!h->scal_flag) {
+    CBA_HIP(hipMemcpyAsync(h->scal_host, h->scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    return *h->scal_host;
+  }
+  const unsigned seq = ++h->scal_seq;
+  k_scalars_out<<<1, 64, 0, h->stream>>>(
+      h->scal, reinterpret_cast<DevScalars*>(h->scal_mapped_dev),
+      reinterpret_cast<unsigned*>(h->scal_mapped_dev + sizeof(DevScalars) + 64), seq);
+  CBA_LAUNCHED();
+  for (unsigned spin = 1;; ++spin) {
+    if (__atomic_load_n(h->scal_flag, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 4095u) == 0) {
+      // a failed kernel never publishes: ask the stream now and then
+      const hipError_t e = hipStreamQuery(h->stream);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(h->scal_flag, __ATOMIC_ACQUIRE) == seq) break;
+        fail(CASPAR_EHIP, "scalar read-back: the stream finished without publishing");
+      }
+      if (e != hipErrorNotReady) CBA_HIP(e);
+    }
+  }
+  DevScalars out;
+  std::memcpy(&out, (const void*)h->scal_host, sizeof(DevScalars));
+  return out;
 }
 
 void upload_cameras_bal(caspar_ba* h, const double* bal, double* cam) {
@@ -835,10 +874,17 @@ static int create_impl(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_
     CBA_HIP(hipGetDevice(&h->device));
     char* ws = (char*)workspace;
     h->scal = (DevScalars*)(ws + plan.scal.off);
-    if (h->static_dev >= 0)
+    if (h->static_dev >= 0) {
       h->scal_host = &h->scal_local;
-    else
-      CBA_HIP(hipHostMalloc((void**)&h->scal_host, sizeof(DevScalars), hipHostMallocDefault));
+    } else {
+      // the struct, then the flag on a line of its own
+      char* pinned = nullptr;
+      CBA_HIP(hipHostMalloc((void**)&pinned, sizeof(DevScalars) + 128, hipHostMallocMapped | hipHostMallocCoherent));
+      h->scal_host = reinterpret_cast<DevScalars*>(pinned);
+      h->scal_flag = reinterpret_cast<unsigned*>(pinned + sizeof(DevScalars) + 64);
+      *h->scal_flag = 0;
+      CBA_HIP(hipHostGetDevicePointer((void**)&h->scal_mapped_dev, pinned, 0));
+    }
     h->partials = (double*)(ws + plan.partials.off);
     h->gauge_rows = (double*)(ws + plan.gauge_rows.off);
     h->cam = (double*)(ws + plan.cam.off);

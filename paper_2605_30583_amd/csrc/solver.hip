@@ -398,6 +398,7 @@ int caspar_ba_solve(caspar_ba* h, const caspar_solve_opts* opts, caspar_solve_st
   CBA_REQUIRE(h != nullptr, "handle is NULL");
   check_device(h);
   solve_impl(h, opts, stats, history);
+  sync(h);  // a read-back by polling leaves the stream drained already; this keeps the contract explicit
   CBA_API_END
 }
 
