@@ -46,6 +46,7 @@ constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kTileMax = 64;         // observations per wave tile
 constexpr int kCamStride = 16;       // doubles per camera row: R(9) t(3) f k1 k2 pad
 constexpr int kCamChunk = 2048;      // camera-major entries per linearisation chunk
+constexpr int kCamSmallChunk = 512;  // at most this many: one wave's chunk (4 per workgroup)
 constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
 constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
 constexpr int kColdRow = 10;         // doubles per cold-camera window row (9 sums, padded to 80 bytes)
@@ -116,9 +117,10 @@ __host__ __device__ inline int tile_steps(int info) { return (info >> 14) & 7; }
 __host__ __device__ inline bool tile_split(int info) { return (info >> 17) & 1; }
 __host__ __device__ inline bool tile_first(int info) { return (info >> 18) & 1; }
 
-// Camera-major linearisation chunk: entries [begin, end) of camera cam.
+// Camera-major linearisation chunk: entries [begin, end) of camera cam, summed
+// into output row `row`.
 struct Chunk {
-  int cam, begin, end, pad;
+  int cam, begin, end, row;
 };
 
 // Points observed more than kTileMax times: their tiles' partial rows.
@@ -192,6 +194,7 @@ struct caspar_ba {
   int n_split_pts = 0;
   int n_orphan_pts = 0;   // points without observations (internal ids [0, n_orphan))
   int n_chunks = 0;
+  int n_big_chunks = 0;  // chunks [0, n_big_chunks) take a workgroup each, the rest a wave
   int no_pad = 0;         // observations rounded up to the Jacobian block
 
   // parameters (float64, internal order)

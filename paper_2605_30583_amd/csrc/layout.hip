@@ -658,16 +658,27 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
     cast_pixels(h);
   }
 
-  // Camera offsets (internal order) and linearisation chunks.
+  // Camera offsets (internal order) and linearisation chunks.  A camera's
+  // entries are cut into chunks of kCamChunk, one workgroup each, while more
+  // than kCamSmallChunk remain; a rest of at most kCamSmallChunk entries
+  // (the whole camera, for most cameras of a heavy-tailed scene) is a small
+  // chunk that one wave sums, four to a workgroup.  The table holds the
+  // workgroup chunks first; each chunk's output row (pad) keeps the rows of
+  // a camera consecutive.
   std::vector<int> cam_off(nc + 1, 0), chunk_off(nc + 1, 0);
-  std::vector<Chunk> chunks;
+  std::vector<Chunk> chunks, small;
+  int row = 0;
   for (int i = 0; i < nc; ++i) {
     const int n = ccnt[cam_i2c[i]];
     cam_off[i + 1] = cam_off[i] + n;
-    for (int b = 0; b < n; b += kCamChunk)
-      chunks.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + std::min(n, b + kCamChunk), 0});
-    chunk_off[i + 1] = (int)chunks.size();
+    int b = 0;
+    for (; n - b > kCamSmallChunk; b += kCamChunk)
+      chunks.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + std::min(n, b + kCamChunk), row++});
+    if (b < n) small.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + n, row++});
+    chunk_off[i + 1] = row;
   }
+  h->n_big_chunks = (int)chunks.size();
+  chunks.insert(chunks.end(), small.begin(), small.end());
   if (chunks.size() > plan.max_chunks) fail(CASPAR_ENOMEM, "internal: chunk table exceeds plan");
   h->n_chunks = (int)chunks.size();
   h2d(h, h->cam_off, cam_off);

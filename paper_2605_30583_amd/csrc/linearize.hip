@@ -385,73 +385,95 @@ __device__ inline int wave_scatter54(double* v, int lane) {
   return ((lane & 32) ? 27 : 0) + pos1;
 }
 
-// Each thread takes the chunk's observations tid, tid + 256, ... (at most
-// kCamChunk / 256 of them): their point indices, points and pixels are all
-// requested before the first block is evaluated.
+// Workgroups [0, n_big) take chunk blockIdx.x with all four waves: thread t
+// takes the chunk's observations t, t + 256, ...  Later workgroups take four
+// small chunks, one per wave: lane l takes observations l, l + 64, ...  In
+// both, a thread holds at most kPer observations, whose point indices,
+// points and pixels are all requested before the first block is evaluated.
 template <typename S>
-__global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chunks,
+__global__ __launch_bounds__(256) void k_lin_cams(const Chunk* __restrict__ chunks, int n_big, int n_chunks,
                                                   const int* __restrict__ cm_pt,
                                                   const S* __restrict__ cm_px,
                                                   const double* __restrict__ cam,
                                                   const S* __restrict__ pts,
                                                   double* __restrict__ rows, int loss, double loss_c) {
   constexpr int kPer = kCamChunk / 256;
+  static_assert(kCamSmallChunk <= kPer * kWave, "a small chunk fits one wave");
   __shared__ double lds[4][kCamRowWidth];
-  const Chunk ch = chunks[blockIdx.x];
   const int tid = threadIdx.x;
-  int jj[kPer];
-  S xp[kPer][3];
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const bool packed = (int)blockIdx.x >= n_big;  // workgroup-uniform
+  const int ci = packed ? n_big + 4 * ((int)blockIdx.x - n_big) + wv : (int)blockIdx.x;
+  if (packed && ci >= n_chunks) return;  // a wave without a chunk (last workgroup only)
+  const Chunk ch = chunks[ci];
+  const int me = packed ? lane : tid;
+  const int step = packed ? kWave : 256;
   using P2 = typename Pair<S>::type;
-  P2 q[kPer];
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) jj[i] = cm_pt[min(ch.begin + tid + 256 * i, ch.end - 1)];
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    load_point<S>(pts, (size_t)jj[i], xp[i]);
-    q[i] = reinterpret_cast<const P2*>(cm_px)[min(ch.begin + tid + 256 * i, ch.end - 1)];
-  }
   const Cam<S> c = load_cam<S>(cam, ch.cam);
+  // A thread's own sums run over at most kPer observations in the working
+  // precision: in the float32-mixed form, whose Jacobian and residual
+  // entries are float32 already, the rounding of eight float32 products
+  // stays far below that of the entries themselves, and the float32 sums
+  // take half the registers (more waves in flight for the gathers).  Every
+  // sum across threads (the wave reduce-scatter, the workgroup, the chunk
+  // rows) is float64.
+  S part[kCamRowWidth];
+#pragma unroll
+  for (int k = 0; k < kCamRowWidth; ++k) part[k] = (S)0;
+  // float64 operands take twice the registers: two rounds of four
+  constexpr int kAhead = sizeof(S) == 4 ? kPer : kPer / 2;
+#pragma unroll
+  for (int h = 0; h < kPer; h += kAhead) {
+    int jj[kAhead];
+    S xp[kAhead][3];
+    P2 q[kAhead];
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i) jj[i] = cm_pt[min(ch.begin + me + step * (h + i), ch.end - 1)];
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i) {
+      load_point<S>(pts, (size_t)jj[i], xp[i]);
+      q[i] = reinterpret_cast<const P2*>(cm_px)[min(ch.begin + me + step * (h + i), ch.end - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kAhead; ++i) {
+      if (ch.begin + me + step * (h + i) >= ch.end) break;
+      S r0, r1, col[12][2];
+      snavely_jacobian<S>(c, xp[i][0], xp[i][1], xp[i][2], (S)q[i].x, (S)q[i].y, r0, r1, col);
+      if (loss != CASPAR_LOSS_TRIVIAL) {
+        // the same weight as the point side computes for this observation
+        double w;
+        (void)robust_rho(loss, loss_c, fma((double)r0, (double)r0, (double)r1 * (double)r1), w);
+        const S sw = (S)sqrt(w);
+        r0 *= sw;
+        r1 *= sw;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          col[j][0] *= sw;
+          col[j][1] *= sw;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) part[k] = fma(col[k][0], r0, fma(col[k][1], r1, part[k]));
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int l = k; l < 9; ++l)
+          part[9 + tri9(k, l)] = fma(col[k][0], col[l][0], fma(col[k][1], col[l][1], part[9 + tri9(k, l)]));
+    }
+  }
   double acc[kCamRowWidth];
 #pragma unroll
-  for (int k = 0; k < kCamRowWidth; ++k) acc[k] = 0.0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    if (ch.begin + tid + 256 * i >= ch.end) break;
-    S r0, r1, col[12][2];
-    snavely_jacobian<S>(c, xp[i][0], xp[i][1], xp[i][2], (S)q[i].x, (S)q[i].y, r0, r1, col);
-    if (loss != CASPAR_LOSS_TRIVIAL) {
-      // the same weight as the point side computes for this observation
-      double w;
-      (void)robust_rho(loss, loss_c, fma((double)r0, (double)r0, (double)r1 * (double)r1), w);
-      const S sw = (S)sqrt(w);
-      r0 *= sw;
-      r1 *= sw;
-#pragma unroll
-      for (int j = 0; j < 9; ++j) {
-        col[j][0] *= sw;
-        col[j][1] *= sw;
-      }
-    }
-    double jc[9][2];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      jc[k][0] = col[k][0];
-      jc[k][1] = col[k][1];
-      acc[k] = fma(jc[k][0], (double)r0, fma(jc[k][1], (double)r1, acc[k]));
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-#pragma unroll
-      for (int l = k; l < 9; ++l)
-        acc[9 + tri9(k, l)] = fma(jc[k][0], jc[l][0], fma(jc[k][1], jc[l][1], acc[9 + tri9(k, l)]));
-  }
-  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  for (int k = 0; k < kCamRowWidth; ++k) acc[k] = (double)part[k];
   const int idx = wave_scatter54(acc, lane);
+  if (packed) {
+    if (idx >= 0) rows[(size_t)ch.row * kCamRowWidth + idx] = acc[0];
+    return;
+  }
   if (idx >= 0) lds[wv][idx] = acc[0];
   __syncthreads();
   if (tid < kCamRowWidth) {
     const double s = lds[0][tid] + lds[1][tid] + lds[2][tid] + lds[3][tid];
-    rows[(size_t)blockIdx.x * kCamRowWidth + tid] = s;
+    rows[(size_t)ch.row * kCamRowWidth + tid] = s;
   }
 }
 
@@ -712,8 +734,10 @@ static void linearize_t(caspar_ba* h) {
     CBA_LAUNCHED();
   }
   if (h->n_chunks > 0) {
-    k_lin_cams<S><<<h->n_chunks, 256, 0, st>>>(h->chunks, h->cm_pt, cm_pixels_of<S>(h), h->cam, ptab, h->chunk_rows,
-                                               h->loss, h->loss_c);
+    const int n_small = h->n_chunks - h->n_big_chunks;
+    k_lin_cams<S><<<h->n_big_chunks + (n_small + 3) / 4, 256, 0, st>>>(
+        h->chunks, h->n_big_chunks, h->n_chunks, h->cm_pt, cm_pixels_of<S>(h), h->cam, ptab, h->chunk_rows, h->loss,
+        h->loss_c);
     CBA_LAUNCHED();
   }
   if (h->nc > 0) {
