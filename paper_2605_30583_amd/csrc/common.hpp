@@ -194,6 +194,7 @@ struct caspar_ba {
   int n_split_pts = 0;
   int n_orphan_pts = 0;   // points without observations (internal ids [0, n_orphan))
   int n_chunks = 0;
+  bool mv_small = false;  // the point-per-lane product runs four-wave workgroups
   int n_big_chunks = 0;  // chunks [0, n_big_chunks) take a workgroup each, the rest a wave
   int no_pad = 0;         // observations rounded up to the Jacobian block
 
@@ -420,6 +421,7 @@ void launch_between_cost(caspar_ba* h, const double* cam);  // its sum r.r into 
 void run_between_product(caspar_ba* h, const void* p, bool pcg_mode);  // bt_rows and pAp partials
 unsigned between_grid(const caspar_ba* h);          // workgroups of the per-camera between kernels
 int matvec_waves(int prec, bool rj);  // waves per workgroup of the fused product
+int matvec_small_waves();              // the same, point-per-lane product on a small problem
 // helpers
 void sync(caspar_ba* h);
 DevScalars read_scalars(caspar_ba* h);

@@ -690,7 +690,11 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   const bool lane_mode = h->rj;  // the product runs point-per-lane over the lane tiles
   const int n_ptiles = lane_mode ? h->n_lane_tiles : h->n_tiles;
   h->L = nc > h->K ? std::min(kColdWin, nc - h->K) : 0;
-  h->G = std::max(1, std::min(groups_per_cu(h->K, h->L) * kNumCUs, (n_ptiles + waves - 1) / waves));
+  // a point-per-lane product that would give fewer workgroups than CUs runs
+  // four-wave workgroups instead: more of them, each with fewer tiles
+  h->mv_small = lane_mode && (n_ptiles + waves - 1) / waves < kNumCUs;
+  const int wg_waves = h->mv_small ? matvec_small_waves() : waves;
+  h->G = std::max(1, std::min(groups_per_cu(h->K, h->L) * kNumCUs, (n_ptiles + wg_waves - 1) / wg_waves));
 
   // Cold cameras (internal id >= K).  Points are ordered by their least
   // observed camera, so the cold observations of one workgroup's tiles

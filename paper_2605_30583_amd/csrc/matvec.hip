@@ -109,6 +109,11 @@ int matvec_waves(int prec, bool rj) {
   return (rj ? MvCfg<float, true>::threads : MvCfg<float, false>::threads) / kWave;
 }
 
+// Workgroup size of the point-per-lane product on a problem too small to
+// give every CU a workgroup of the full size: four waves.
+constexpr int kLanesSmallThreads = 256;
+int matvec_small_waves() { return kLanesSmallThreads / kWave; }
+
 // Stores that only some lanes need are issued by every lane through a buffer
 // resource: a lane with nothing to write passes an offset past the end of
 // the buffer and the hardware drops its write.  Each loop iteration then
@@ -438,8 +443,8 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 // numbered per tile in (iteration, lane) order.  A whole point writes its row
 // of w directly (64 consecutive points per tile: coalesced); a piece writes a
 // split row that k_matvec_final adds up.
-template <typename S>
-__global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
+template <typename S, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     int n_tiles, int G, const int2* __restrict__ ltiles, int n_units, const int* __restrict__ unit_obs,
     const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const uint32_t* __restrict__ meta,
     const S* __restrict__ pts_s, const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
@@ -447,7 +452,6 @@ __global__ __launch_bounds__((MvCfg<S, true>::threads)) void k_matvec_lanes(
     int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows, double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L,
     unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
-  constexpr int THREADS = MvCfg<S, true>::threads;
   constexpr int WAVES = THREADS / kWave;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
@@ -783,22 +787,27 @@ __global__ __launch_bounds__(256) void k_matvec_final(
 
 template <typename S, bool RJ>
 static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScalars* scp) {
-  constexpr int T = MvCfg<S, RJ>::threads;
+  constexpr int T_FULL = MvCfg<S, RJ>::threads;
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = matvec_lds_bytes(h->K, h->L);
   auto kern = k_matvec<S, RJ>;
-  // recomputed blocks run the point-per-lane kernel
-  const void* kptr = RJ ? (const void*)k_matvec_lanes<S> : (const void*)kern;
+  // recomputed blocks run the point-per-lane kernel, in small workgroups on
+  // a small problem
+  const bool small = RJ && h->mv_small;
+  auto lanes = small ? k_matvec_lanes<S, kLanesSmallThreads> : k_matvec_lanes<S, MvCfg<S, true>::threads>;
+  const int T = small ? kLanesSmallThreads : T_FULL;
+  const void* kptr = RJ ? (const void*)lanes : (const void*)kern;
   // the dynamic-LDS limit belongs to the kernel on a device: raised only when
   // a launch needs more than it was last set to (not at every launch)
   {
     static std::mutex mu;
-    static std::vector<size_t> lds_set;
+    static std::vector<size_t> lds_set[2];  // [full, small workgroups]
     std::lock_guard<std::mutex> lock(mu);
-    if ((size_t)h->device >= lds_set.size()) lds_set.resize((size_t)h->device + 1, 65536);
-    if (lds > lds_set[h->device]) {
+    std::vector<size_t>& set = lds_set[small ? 1 : 0];
+    if ((size_t)h->device >= set.size()) set.resize((size_t)h->device + 1, 65536);
+    if (lds > set[h->device]) {
       CBA_HIP(hipFuncSetAttribute(kptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      lds_set[h->device] = lds;
+      set[h->device] = lds;
     }
   }
   // with timing on, the launch itself stamps the events (no extra packets
@@ -806,7 +815,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   hipEvent_t e0, e1;
   timing_events(h, &e0, &e1);
   if constexpr (RJ) {
-    hipExtLaunchKernelGGL(k_matvec_lanes<S>, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u,
+    hipExtLaunchKernelGGL(lanes, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u,
                           h->n_lane_tiles, h->G, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt, h->unit_row,
                           h->meta, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D,
                           lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows, (S*)h->cold_rows,
