@@ -404,7 +404,7 @@ def main():
                     "frac": tflops / ALU_PEAK_TFLOPS if tflops else None}
     roofline.update({
         "traffic": counter_traffic(a.workload, a.precision, a.jacobian),
-        "kernel": "k_matvec",
+        "kernel": "k_matvec_lanes" if a.jacobian == "recompute" else "k_matvec",
         "avg_ms": mv_avg_ms,
         "launches": tim["matvec_launches"],
         "timed_every": a.time_every,
