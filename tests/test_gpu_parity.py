@@ -177,3 +177,29 @@ def test_mixed_precision_cold_rows_and_products(rj):
     w_ref = linear.matvec(ref.J, ref.D, 1e-2, p)
     assert rel(w.cpu(), w_ref) <= 2e-5
     assert abs(pap - p @ w_ref) <= 2e-5 * abs(p @ w_ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
+def test_product_repeats_to_rounding(rj, precision):
+    """The hot-camera and window sums are LDS atomic adds in the order the
+    waves reach them, so repeated products may differ in the camera entries
+    at the rounding level: float64 sums of at most a few thousand terms (bar
+    1e-13), and in the float32-mixed form the rounding of each workgroup's
+    float64 sum to float32 can move by one unit in the last place (bar 1e-6).
+    The point entries are summed in registers or by fixed-order scans and
+    split rows, so they repeat bit for bit."""
+    from synth import make_scene
+    sc = make_scene(2300, 6000, 17, k_values=(2, 3, 4), k_probs=(0.3, 0.4, 0.3), zipf_s=0.9)
+    px = observed_pixels(sc)
+    ba = handle_for(sc, px, precision=precision, rj=rj)
+    assert ba.layout_info()["cold_obs"] > 0
+    ba.linearize(outputs=False)
+    p = t64(np.random.default_rng(13).normal(size=9 * sc.n_cams + 3 * sc.n_points))
+    ws = [ba.matvec(1e-2, p)[0].cpu().numpy() for _ in range(5)]
+    nc9 = 9 * sc.n_cams
+    bar = 1e-13 if precision == 0 else 1e-6
+    for w in ws[1:]:
+        assert np.array_equal(w[nc9:], ws[0][nc9:])
+        assert rel(w[:nc9], ws[0][:nc9]) <= bar
+    ba.close()
