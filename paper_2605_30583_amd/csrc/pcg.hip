@@ -251,11 +251,17 @@ __device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double
   sc->last_x = sc->done;
 }
 
-// r -= alpha w, z = M^-1 r, and the sums r^T r, r^T z.  Thread i takes
-// camera block i and point block i (grid-stride), each with its whole block
-// in registers (vector loads of 3 or 9 consecutive values).  Workgroup sums
-// go to the partial slots.  The x step of the same iteration is taken by the
-// direction kernel, which reads p anyway.
+// r -= alpha w, z = M^-1 r, and the sums r^T r, r^T z.  A camera block
+// takes nine lanes of one wave, seven blocks to a wave (lane 9 j + k: row k
+// of block j): each lane recomputes the block's nine updated r values and
+// applies row k of M^-1 (the same operations, in the same order, as the
+// whole-block apply), so a 9x9 block does not serialise one thread on 45
+// loads and 81 multiply-adds, which on a small problem is the kernel's
+// critical path.  The nine lanes of a block are in one wave, so all of them
+// read r before any writes it.  Thread i also takes point block i
+// (grid-stride, its r and w in registers).  Workgroup sums go to the partial
+// slots.  The x step of the same iteration is taken by the direction kernel,
+// which reads p anyway.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __restrict__ Mc,
                                                     const S* __restrict__ Mp, S* __restrict__ r,
@@ -268,20 +274,29 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
   double rz = 0.0, rr = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  for (int64_t c = i0; c < nc; c += stride) {
-    const size_t o = 9 * (size_t)c;
-    S wv[9], rv[9];
+  const int lane = threadIdx.x & (kWave - 1);
+  if (lane < 63) {
+    const int64_t n_groups = ((int64_t)nc + 6) / 7;
+    const int j = lane / 9, k = lane - 9 * (lane / 9);
+    for (int64_t g = i0 / kWave; g < n_groups; g += stride / kWave) {
+      const int64_t c = 7 * g + j;
+      if (c >= nc) continue;
+      const size_t o = 9 * (size_t)c;
+      S rv[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      wv[k] = w[o + k];
-      rv[k] = r[o + k];
-    }
+      for (int l = 0; l < 9; ++l) rv[l] = (S)fma(-alpha, (double)w[o + l], (double)r[o + l]);
+      const S* __restrict__ m = Mc + 45 * c;
+      S zk = (S)0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      rv[k] = (S)fma(-alpha, (double)wv[k], (double)rv[k]);
-      r[o + k] = rv[k];
+      for (int l = 0; l < 9; ++l) zk = fma(m[k <= l ? tri_idx(9, k, l) : tri_idx(9, l, k)], rv[l], zk);
+      S rk = rv[0];
+#pragma unroll
+      for (int l = 1; l < 9; ++l) rk = l == k ? rv[l] : rk;
+      r[o + k] = rk;
+      z[o + k] = zk;
+      rz = fma((double)rk, (double)zk, rz);
+      rr = fma((double)rk, (double)rk, rr);
     }
-    block_apply<S, 9>(Mc + 45 * c, rv, z + o, rz, rr);
   }
   const S* __restrict__ wp = w + 9 * (size_t)nc;
   S* __restrict__ rp = r + 9 * (size_t)nc;
