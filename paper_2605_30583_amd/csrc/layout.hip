@@ -663,19 +663,37 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   // than kCamSmallChunk remain; a rest of at most kCamSmallChunk entries
   // (the whole camera, for most cameras of a heavy-tailed scene) is a small
   // chunk that one wave sums, four to a workgroup.  The table holds the
-  // workgroup chunks first; each chunk's output row (pad) keeps the rows of
-  // a camera consecutive.
+  // workgroup chunks first; each chunk's output row keeps the rows of a
+  // camera consecutive.  A camera's entries are in point order, and the
+  // points of a much-observed camera spread over the whole point order, so
+  // the workgroup chunks are launched in the order of where they sit inside
+  // their camera (the middle entry's fraction of the camera's entries): the
+  // chunks in flight together gather from one region of the points, which
+  // then stays in the L2 caches, instead of each camera's chunks sweeping
+  // all points in turn.
   std::vector<int> cam_off(nc + 1, 0), chunk_off(nc + 1, 0);
   std::vector<Chunk> chunks, small;
+  std::vector<std::pair<double, int>> order;  // (position inside the camera, chunk)
   int row = 0;
   for (int i = 0; i < nc; ++i) {
     const int n = ccnt[cam_i2c[i]];
     cam_off[i + 1] = cam_off[i] + n;
     int b = 0;
-    for (; n - b > kCamSmallChunk; b += kCamChunk)
-      chunks.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + std::min(n, b + kCamChunk), row++});
+    for (; n - b > kCamSmallChunk; b += kCamChunk) {
+      const int e = std::min(n, b + kCamChunk);
+      order.emplace_back(0.5 * (b + e) / n, (int)chunks.size());
+      chunks.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + e, row++});
+    }
     if (b < n) small.push_back(Chunk{i, cam_off[i] + b, cam_off[i] + n, row++});
     chunk_off[i + 1] = row;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first < b.first; });
+  {
+    std::vector<Chunk> sorted;
+    sorted.reserve(chunks.size());
+    for (const auto& o : order) sorted.push_back(chunks[o.second]);
+    chunks.swap(sorted);
   }
   h->n_big_chunks = (int)chunks.size();
   chunks.insert(chunks.end(), small.begin(), small.end());
