@@ -7,15 +7,18 @@
 //
 // The paper's shared-add accessor (Section IV-A) reduces per block and then
 // issues one global atomic per unique index.  On MI355X global FP64 atomics
-// sustain only ~22 G/s, far below the rate observations stream in, so this
-// kernel keeps all camera accumulation on chip instead:
-//  * persistent workgroups (1024 threads) each own a contiguous range of wave
-//    tiles and keep float64 accumulators for the K most observed cameras in
-//    LDS (ds_add_f64), flushed once per workgroup as plain rows;
+// sustain only ~22 G/s, far below the rate observations stream in, so these
+// kernels keep all camera accumulation on chip instead:
+//  * persistent workgroups each own a contiguous range of wave tiles and keep
+//    float64 accumulators for the K most observed cameras (and a window of
+//    cold ones) in LDS (ds_add_f64), flushed once per workgroup as plain rows;
 //  * observations of the remaining cameras write their 9-vector to a row of
 //    their own (ballot-ranked inside the wave, so rows stay coalesced);
-//  * points are contiguous inside a tile: an in-wave segmented scan sums their
-//    contributions and the first lane of each point writes w_j directly.
+//  * stored blocks (k_matvec): one observation per lane; points are
+//    contiguous inside a tile, so an in-wave segmented scan sums their
+//    contributions and the first lane of each point writes w_j directly;
+//  * recomputed blocks (k_matvec_lanes): one point per lane, looping over its
+//    observations with the point sum in registers.
 // A second small kernel adds the per-workgroup rows and cold rows of each
 // camera in a fixed order, handles split and orphan points and turns the
 // p^T A p partials into alpha for PCG.  The LDS sums themselves are atomic
