@@ -136,3 +136,38 @@ def test_large_workload_pcg_residual(large):
         assert true_rel <= slack * tol
     ba32.close()
     ba64.close()
+
+
+def test_large_workload_adjoint_scatter(large):
+    """The backward at full size (float64, recomputed blocks): it solves
+    (J^T J + lambda D) v = g for the tangent gradient g of the loss (sum of
+    squared point coordinates, at the start parameters) and returns
+    dL/dpx_o = J_o v in caller order.  The same solve through the PCG hook
+    gives v; on sampled observations (the most observed camera's, a camera
+    outside the LDS set's, and random ones) the oracle's own blocks J_o at the
+    same parameters times that v must give the backward's rows.  The two
+    solves run the same PCG to 1e-10 and differ only by the order of the
+    camera sums (rounding), the blocks by float64 evaluation: bar 1e-9."""
+    sc, px, st0, cost, cams, pts = large
+    lam = 1e-4
+    ba = handle_for(sc, px, 0, rj=True)
+    _, pts_t = ba.get_params()
+    b = np.zeros(9 * sc.n_cams + 3 * sc.n_points)
+    b[9 * sc.n_cams:] = 2.0 * pts_t.cpu().numpy().ravel()
+    v, iters, rel_res = ba.pcg(lam, t64(b), 1e-10, 5000)
+    assert rel_res <= 1e-10
+    grad = ba.backward(None, 2.0 * pts_t, lambda_adj=lam, pcg_tol=1e-10, max_pcg_iters=5000).cpu().numpy()
+    assert ba.last_backward_rel_resid <= 1e-10
+    ba.close()
+    counts = np.bincount(sc.obs_cam, minlength=sc.n_cams)
+    order = np.argsort(-counts, kind="stable")
+    rng = np.random.default_rng(31)
+    sel = np.concatenate([np.flatnonzero(sc.obs_cam == order[0])[:500], np.flatnonzero(sc.obs_cam == order[5000])[:200],
+                          rng.choice(sc.n_obs, 2000, replace=False)])
+    oc, op = sc.obs_cam[sel], sc.obs_pt[sel]
+    _, Jc, Jp = camera.linearize(st0, oc, op, px[sel])
+    v = v.cpu().numpy()
+    vc = v[:9 * sc.n_cams].reshape(-1, 9)[oc]
+    vp = v[9 * sc.n_cams:].reshape(-1, 3)[op]
+    ref = np.einsum("oij,oj->oi", Jc, vc) + np.einsum("oij,oj->oi", Jp, vp)
+    assert rel(grad[sel], ref) <= 1e-9
