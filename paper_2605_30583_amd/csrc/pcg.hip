@@ -180,14 +180,38 @@ __global__ __launch_bounds__(256) void k_pcg_init(int nc, int np, const S* __res
                                                   double* __restrict__ partials) {
   __shared__ double red[4];
   double rz = 0.0, rr = 0.0;
-  const int64_t nb = (int64_t)nc + np;
-  for (int64_t blk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; blk < nb;
-       blk += (int64_t)gridDim.x * blockDim.x) {
-    if (blk < nc)
-      init_block<S, 9>(Mc + 45 * blk, b, sign, 9 * (size_t)blk, x, r, z, p, rz, rr);
-    else
-      init_block<S, 3>(Mp + 6 * (blk - nc), b, sign, 9 * (size_t)nc + 3 * (size_t)(blk - nc), x, r, z, p, rz, rr);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // camera blocks: nine lanes of one wave each (row k of M^-1 per lane, the
+  // whole-block apply's operations in its order), seven blocks to a wave
+  const int lane = threadIdx.x & (kWave - 1);
+  if (lane < 63) {
+    const int64_t n_groups = ((int64_t)nc + 6) / 7;
+    const int j = lane / 9, k = lane - 9 * (lane / 9);
+    for (int64_t g = i0 / kWave; g < n_groups; g += stride / kWave) {
+      const int64_t c = 7 * g + j;
+      if (c >= nc) continue;
+      const size_t o = 9 * (size_t)c;
+      S rv[9];
+#pragma unroll
+      for (int l = 0; l < 9; ++l) rv[l] = (S)(sign * (double)b[o + l]);
+      const S* __restrict__ m = Mc + 45 * c;
+      S zk = (S)0;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) zk = fma(m[k <= l ? tri_idx(9, k, l) : tri_idx(9, l, k)], rv[l], zk);
+      S rk = rv[0];
+#pragma unroll
+      for (int l = 1; l < 9; ++l) rk = l == k ? rv[l] : rk;
+      r[o + k] = rk;
+      x[o + k] = (S)0;
+      z[o + k] = zk;
+      p[o + k] = zk;
+      rz = fma((double)rk, (double)zk, rz);
+      rr = fma((double)rk, (double)rk, rr);
+    }
   }
+  for (int64_t i = i0; i < np; i += stride)
+    init_block<S, 3>(Mp + 6 * i, b, sign, 9 * (size_t)nc + 3 * (size_t)i, x, r, z, p, rz, rr);
   const double a = block_sum(rz, red);
   const double c = block_sum(rr, red);
   if (threadIdx.x == 0) {
