@@ -148,7 +148,8 @@ struct DevScalars {
   double red[8];
   int err;
   int last_x;  // the iteration that set `done` made a valid update whose x step is still due
-  int pad1[2];
+  unsigned ticket;  // workgroups of the PCG update done so far (its last one sets the scalars)
+  int pad1;
 };
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXITER = 3, PCG_ZERO_RHS = 4 };
 

@@ -242,6 +242,7 @@ __global__ void k_pcg_scalar0(int n, const double* __restrict__ partials, double
     sc->done = 0;
     sc->reason = PCG_RUNNING;
     sc->last_x = 0;
+    sc->ticket = 0;
     if (c == 0.0) {
       sc->done = 1;
       sc->reason = PCG_ZERO_RHS;
@@ -286,11 +287,19 @@ __device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double
 // (grid-stride, its r and w in registers).  Workgroup sums go to the partial
 // slots.  The x step of the same iteration is taken by the direction kernel,
 // which reads p anyway.
-template <typename S>
+//
+// LAST (a small problem, few workgroups): instead of a separate launch of
+// k_pcg_scalar1, the last workgroup to finish sums the partials and sets the
+// scalars.  Each workgroup releases its partials with a device-scope fence
+// before taking a ticket; the one that takes the last ticket acquires them
+// with another fence.  A device-scope fence writes back the L2 of the
+// workgroup's XCD, which on a large problem (megabytes of r and z in flight)
+// costs more than the launch it saves.
+template <typename S, bool LAST>
 __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __restrict__ Mc,
                                                     const S* __restrict__ Mp, S* __restrict__ r,
                                                     S* __restrict__ z, const S* __restrict__ w,
-                                                    const DevScalars* __restrict__ sc,
+                                                    DevScalars* __restrict__ sc,
                                                     double* __restrict__ partials) {
   __shared__ double red[4];
   if (sc->done) return;
@@ -345,6 +354,28 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
   if (threadIdx.x == 0) {
     partials[(size_t)blockIdx.x * kPartialWidth] = sa;
     partials[(size_t)blockIdx.x * kPartialWidth + 1] = sz;
+  }
+  if constexpr (LAST) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this workgroup's partials
+      last = atomicAdd(&sc->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+      __threadfence();  // acquire every workgroup's partials
+      double a = 0.0, c = 0.0;
+      for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        a += partials[(size_t)i * kPartialWidth];
+        c += partials[(size_t)i * kPartialWidth + 1];
+      }
+      a = block_sum(a, red);
+      c = block_sum(c, red);
+      if (threadIdx.x == 0) {
+        pcg_scalars_after_update(sc, a, c);
+        sc->ticket = 0;
+      }
+    }
   }
 }
 
@@ -563,6 +594,10 @@ void run_bj_apply(caspar_ba* h, const void* r, void* z) {
   CBA_LAUNCHED();
 }
 
+// The update sets the PCG scalars itself (no k_pcg_scalar1 launch) up to
+// this many workgroups (points or cameras up to 256 per workgroup).
+constexpr unsigned kLastGroupMaxGroups = 256;
+
 template <typename S>
 static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double tol, int max_iters,
                  int check_every, double* rel_resid, int first_batch) {
@@ -599,10 +634,15 @@ static int pcg_t(caspar_ba* h, double lambda, const S* b, bool negate, double to
       // the first product pads the camera rows of p itself; later ones use
       // the rows written by k_pcg_p
       run_matvec(h, lambda, p, w, true, launched + k == 0);
-      k_pcg_update<S><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, r, z, w, h->scal, h->partials);
-      CBA_LAUNCHED();
-      k_pcg_scalar1<<<1, 1024, 0, st>>>((int)ug, h->partials, h->scal);
-      CBA_LAUNCHED();
+      if (ug <= kLastGroupMaxGroups) {
+        k_pcg_update<S, true><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, r, z, w, h->scal, h->partials);
+        CBA_LAUNCHED();
+      } else {
+        k_pcg_update<S, false><<<ug, 256, 0, st>>>(h->nc, h->np, Mc, Mp, r, z, w, h->scal, h->partials);
+        CBA_LAUNCHED();
+        k_pcg_scalar1<<<1, 1024, 0, st>>>((int)ug, h->partials, h->scal);
+        CBA_LAUNCHED();
+      }
       k_pcg_p<S><<<pg, 256, 0, st>>>(N, h->nc, z, p, x, (S*)h->p_cam, cam_row_stride<S>(h), cam_row_p_off(h),
                                      h->scal);
       CBA_LAUNCHED();
