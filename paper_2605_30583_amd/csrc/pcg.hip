@@ -380,9 +380,10 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
 }
 
 // Sums the update's partials in slot order (deterministic) and sets the PCG
-// scalars.  A separate single-workgroup launch: folding this into the
-// update's last workgroup needs a device-scope fence per workgroup, which
-// writes back the L2 of its XCD and costs more than the launch.
+// scalars.  A separate single-workgroup launch on a large problem: folding
+// this into the update's last workgroup (as the small-problem variant does)
+// needs a device-scope fence per workgroup, which writes back the L2 of its
+// XCD and there costs more than the launch.
 __global__ void k_pcg_scalar1(int n, const double* __restrict__ partials, DevScalars* sc) {
   __shared__ double red[16];
   if (sc->done) return;
