@@ -87,7 +87,8 @@ constexpr int kProdCamRow = 20;
 constexpr int kProdCamP = 10;  // offset of p in the row
 
 // Camera row of the product's input vector p with stored blocks: its 9 values
-// padded to 10 doubles (5 x 16 B) or 12 floats (3 x 16 B).
+// padded to 10 doubles (5 x 16 B) or 16 floats (64 B, gathered by quads of
+// lanes).
 template <typename S>
 struct CamPad;
 template <>
@@ -96,7 +97,7 @@ struct CamPad<double> {
 };
 template <>
 struct CamPad<float> {
-  static constexpr int n = 12;
+  static constexpr int n = 16;
 };
 
 // Wave tile: a run of whole points (or one slice of a point with more than

@@ -185,18 +185,20 @@ __global__ __launch_bounds__(256) void k_lin_points(int n_tiles, const Tile* __r
     const int oa = ta.obs_begin + min(lane, na - 1);
     const int ob = tb.obs_begin + min(lane, max(nb, 1) - 1);
     const uint32_t ma = meta[oa], mb = meta[ob];
-    // every load of both tiles first (camera rows in the working precision:
-    // these per-lane gathers bound the kernel, so float32 rows halve them);
-    // the barrier keeps the first tile's conversions from waiting on its
-    // loads before the second tile's are issued
-    const Cam<S> ca = load_cam_s<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)));
-    const Cam<S> cb = load_cam_s<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)));
+    // every load of both tiles first (camera rows in the working precision,
+    // float32 ones gathered by quads of lanes: these gathers bound the
+    // kernel); the barrier keeps the first tile's conversions from waiting on
+    // its loads before the second tile's are issued
+    CamReq<S> rqa, rqb;
+    cam_request<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)), rqa);
+    cam_request<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)), rqb);
     S xa[3], xb[3];
     load_point<S>(pts, (size_t)(ta.pt_begin + (int)(ma >> kCamBits)), xa);
     load_point<S>(pts, (size_t)(tb.pt_begin + (int)(mb >> kCamBits)), xb);
     const P2 qa = reinterpret_cast<const P2*>(px)[oa];
     const P2 qb = reinterpret_cast<const P2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
+    const Cam<S> ca = cam_take<S>(rqa), cb = cam_take<S>(rqb);
     tile(ta, na, ma, ca, xa, qa, oa);
     if (t2 < n_tiles) tile(tb, nb, mb, cb, xb, qb, ob);
   }
@@ -244,15 +246,18 @@ __global__ __launch_bounds__(256) void k_lin_lanes(int n_tiles, const int2* __re
     double v[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) v[a] = 0.0;
-    Cam<S> c = load_cam_s<S>(camtab, (int)(meta[ob] & cmask));
+    CamReq<S> rq;
+    cam_request<S>(camtab, (int)(meta[ob] & cmask), rq);
     P2 q = reinterpret_cast<const P2*>(px)[ob];
     uint32_t m1 = meta[obs(1)];
     for (int it = 0; it < trip; ++it) {
       const bool act = it < k;
       const int o = obs(it);
+      // this observation's camera (every lane: float32 rows come by quads)
+      const Cam<S> c = cam_take<S>(rq);
       // requests: the next observation's camera row and pixel, the meta word
       // of the one after
-      const Cam<S> cn = load_cam_s<S>(camtab, (int)(m1 & cmask));
+      cam_request<S>(camtab, (int)(m1 & cmask), rq);
       const P2 qn = reinterpret_cast<const P2*>(px)[obs(it + 1)];
       const uint32_t m2 = meta[obs(it + 2)];
       if (act) {
@@ -288,7 +293,6 @@ __global__ __launch_bounds__(256) void k_lin_lanes(int n_tiles, const int2* __re
         v[7] = fma(jp[1][0], jp[2][0], fma(jp[1][1], jp[2][1], v[7]));
         v[8] = fma(jp[2][0], jp[2][0], fma(jp[2][1], jp[2][1], v[8]));
       }
-      c = cn;
       q = qn;
       m1 = m2;
     }
@@ -558,12 +562,13 @@ __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restric
     const int oa = ta.obs_begin + min(lane, na - 1);
     const int ob = tb.obs_begin + min(lane, max(nb, 1) - 1);
     const uint32_t ma = meta[oa], mb = meta[ob];
-    // every load of both tiles first (camera rows in the working precision:
-    // these per-lane gathers bound the kernel, so float32 rows halve them);
-    // the barrier keeps the first tile's conversions from waiting on its
-    // loads before the second tile's are issued
-    const Cam<S> ca = load_cam_s<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)));
-    const Cam<S> cb = load_cam_s<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)));
+    // every load of both tiles first (camera rows in the working precision,
+    // float32 ones gathered by quads of lanes: these gathers bound the
+    // kernel); the barrier keeps the first tile's conversions from waiting on
+    // its loads before the second tile's are issued
+    CamReq<S> rqa, rqb;
+    cam_request<S>(camtab, (int)(ma & ((1u << kCamBits) - 1)), rqa);
+    cam_request<S>(camtab, (int)(mb & ((1u << kCamBits) - 1)), rqb);
     const double* Xa = X + 3 * (size_t)(ta.pt_begin + (int)(ma >> kCamBits));
     const double* Xb = X + 3 * (size_t)(tb.pt_begin + (int)(mb >> kCamBits));
     const double xa[3] = {Xa[0], Xa[1], Xa[2]}, xb[3] = {Xb[0], Xb[1], Xb[2]};
@@ -571,6 +576,7 @@ __global__ __launch_bounds__(256) void k_cost(int n_tiles, const Tile* __restric
     const P2 qa = reinterpret_cast<const P2*>(px)[oa];
     const P2 qb = reinterpret_cast<const P2*>(px)[ob];
     __builtin_amdgcn_sched_barrier(0);
+    const Cam<S> ca = cam_take<S>(rqa), cb = cam_take<S>(rqb);
     // rho(|r|^2) of one observation (|r|^2 with the trivial loss)
     auto term = [&](S r0, S r1) {
       const double sq = fma((double)r0, (double)r0, (double)r1 * (double)r1);

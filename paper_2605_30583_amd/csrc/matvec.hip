@@ -59,32 +59,43 @@ __device__ inline void load_cam_row<double>(const double* __restrict__ rows, int
     out[2 * i + 1] = v.y;
   }
 }
+// float32 rows (64 bytes) come in two halves, as camera rows do in the
+// linearisation: requested by quads of lanes, then exchanged within the quad
+// (both with every lane active).
+template <typename S>
+struct CamRowReq;
 template <>
-__device__ inline void load_cam_row<float>(const float* __restrict__ rows, int c, float* out) {
-  const float4* r = reinterpret_cast<const float4*>(rows + (size_t)c * CamPad<float>::n);
+struct CamRowReq<float> {
+  QuadRows r;
+};
+template <>
+struct CamRowReq<double> {
+  double v[CamPad<double>::n];
+};
+__device__ inline void cam_row_request(const float* __restrict__ rows, int c, CamRowReq<float>& q) {
+  static_assert(CamPad<float>::n == 16, "64-byte float32 rows");
+  quad_rows_request(rows, c, q.r);
+}
+__device__ inline void cam_row_request(const double* __restrict__ rows, int c, CamRowReq<double>& q) {
+  load_cam_row<double>(rows, c, q.v);
+}
+__device__ inline void cam_row_take(CamRowReq<float>& q, float (&out)[CamPad<float>::n]) { quad_rows_take(q.r, out); }
+__device__ inline void cam_row_take(CamRowReq<double>& q, double (&out)[CamPad<double>::n]) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const float4 v = r[i];
-    out[4 * i] = v.x;
-    out[4 * i + 1] = v.y;
-    out[4 * i + 2] = v.z;
-    out[4 * i + 3] = v.w;
-  }
+  for (int k = 0; k < CamPad<double>::n; ++k) out[k] = q.v[k];
 }
 
-// Launch shape and pipeline depth of the fused product.  16 waves per
-// workgroup; recomputing float64 blocks needs more than 128 VGPRs, so that
-// variant runs 8-wave workgroups (256 VGPRs per lane).  One tile ahead of the
-// one being computed, the product requests
+// Launch shape of the fused product (RJ: recomputed blocks, the
+// point-per-lane kernel) and pipeline depth of the stored-block kernel.  16
+// waves per workgroup; the float64 point-per-lane kernel needs more than 128
+// VGPRs, so it runs 8-wave workgroups (256 VGPRs per lane).  One tile ahead of
+// the one being computed, the stored-block kernel requests
 //   prefetch_j:   the stored Jacobian chunks (float32: 24 VGPRs; float64 has
 //                 no room and loads them at the end of the previous tile);
 //   prefetch_pt:  p and D of the tile's points (otherwise loaded with the
 //                 camera gathers of the tile itself);
-//   prefetch_cam: the camera rows (p alone with stored blocks; with
-//                 recomputed blocks one row holds the camera parameters and
-//                 p) and, with recomputed blocks, the point (otherwise
-//                 gathered at the start of the tile, with their latency
-//                 exposed; float64 stored blocks would spill).
+//   prefetch_cam: the camera rows of p (otherwise gathered at the start of
+//                 the tile, with their latency exposed; float64 would spill).
 template <typename S, bool RJ>
 struct MvCfg {
   static constexpr int threads = 1024;
@@ -102,9 +113,6 @@ struct MvCfg<double, false> {
 template <>
 struct MvCfg<double, true> {
   static constexpr int threads = 512;
-  static constexpr bool prefetch_j = false;
-  static constexpr bool prefetch_pt = true;
-  static constexpr bool prefetch_cam = true;
 };
 
 int matvec_waves(int prec, bool rj) {
@@ -165,8 +173,8 @@ __device__ inline void store3(__amdgpu_buffer_rsrc_t rs, unsigned off, const dou
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[2]), rs, (int)off + 16, 0, 0);
 }
 
-template <typename S, bool RJ>
-__global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
+template <typename S>
+__global__ __launch_bounds__((MvCfg<S, false>::threads)) void k_matvec(
     int n_tiles, int G, const Tile* __restrict__ tiles, const uint32_t* __restrict__ meta,
     const void* __restrict__ J, const S* __restrict__ pts_s,
     const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
@@ -174,13 +182,12 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows,
     double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L, int local_base,
-    unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
-  constexpr int THREADS = MvCfg<S, RJ>::threads;
+    unsigned w_pt_bytes, unsigned cold_bytes) {
+  constexpr int THREADS = MvCfg<S, false>::threads;
   constexpr int WAVES = THREADS / kWave;
-  constexpr bool PREFETCH_J = MvCfg<S, RJ>::prefetch_j;
-  constexpr bool PF_PT = MvCfg<S, RJ>::prefetch_pt;
-  constexpr bool PF_CAM = MvCfg<S, RJ>::prefetch_cam;
-  static_assert(PF_CAM || !RJ, "recomputed blocks prefetch their camera rows");
+  constexpr bool PREFETCH_J = MvCfg<S, false>::prefetch_j;
+  constexpr bool PF_PT = MvCfg<S, false>::prefetch_pt;
+  constexpr bool PF_CAM = MvCfg<S, false>::prefetch_cam;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
   // the P most observed cameras get kPrivCopies private copies (copy = lane
@@ -235,19 +242,15 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     // these, so the set being computed and the set being filled swap roles
     // instead of being copied.
     struct Regs {
-      S col[12][2];             // Jacobian columns (stored blocks)
-      S pjv[3], dpv[3];         // p and D of the observation's point
-      S pcv[CamPad<S>::n];      // camera row of p (stored blocks)
-      S crow[kProdCamRow];      // camera row: parameters and p (recomputed blocks)
-      S xj[3];                  // the point (recomputed blocks)
-      S wgt;                    // IRLS weight (recomputed blocks, robust loss)
+      S col[12][2];         // Jacobian columns
+      S pjv[3], dpv[3];     // p and D of the observation's point
+      CamRowReq<S> pcr;     // camera row of p, as requested
     };
     // the requests made one tile ahead (tile descriptor T, nt observations,
     // meta word mm of this lane)
     auto request = [&](Regs& R, const Tile& T, int nt, uint32_t mm) {
-      if (PREFETCH_J && !RJ) JStore<S>::load(J, T.obs_begin + olane(nt), R.col);
-      // stored blocks are stored sqrt(w)-scaled; recomputed ones take w here
-      if (RJ && wts != nullptr) R.wgt = wts[T.obs_begin + olane(nt)];
+      // (blocks are stored sqrt(w)-scaled under a robust loss)
+      if (PREFETCH_J) JStore<S>::load(J, T.obs_begin + olane(nt), R.col);
       if (PF_PT) {
         const size_t b = 3 * (size_t)(T.pt_begin + (int)(mm >> kCamBits));
 #pragma unroll
@@ -256,15 +259,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
           R.dpv[k] = dp_base[b + k];
         }
       }
-      if (PF_CAM) {
-        const int c = (int)(mm & ((1u << kCamBits) - 1));
-        if (RJ) {
-          load_prod_cam<S>(p_cam, c, R.crow);
-          load_point<S>(pts_s, (size_t)(T.pt_begin + (int)(mm >> kCamBits)), R.xj);
-        } else {
-          load_cam_row<S>(p_cam, c, R.pcv);
-        }
-      }
+      if (PF_CAM) cam_row_request(p_cam, (int)(mm & ((1u << kCamBits) - 1)), R.pcr);
     };
     Tile tl = tiles[t], tln = tile_at(t + WAVES), tlnn = tile_at(t + 2 * WAVES);
     int n = tile_nobs(tl.info);
@@ -272,7 +267,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
     uint32_t mn = meta[tln.obs_begin + olane(nobs(t + WAVES, tln))];
     Regs A, B;
     request(A, tl, n, m);
-    if (!RJ && !PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), A.col);
+    if (!PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), A.col);
 
     // One tile: compute tile t from cur while the next tile's data comes
     // into nxt.  Returns true after the wave's last tile.
@@ -284,7 +279,11 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       const int lp = act ? lp_raw : 100 + lane;
       // 1. gathers of the current tile that the configuration does not
       //    prefetch
-      if (!PF_CAM) load_cam_row<S>(p_cam, ci_raw, cur.pcv);
+      if (!PF_CAM) cam_row_request(p_cam, ci_raw, cur.pcr);
+      // the camera row of p, taken by every lane (float32 rows come by quads)
+      // before the next tile's requests claim their registers
+      S pcv[CamPad<S>::n];
+      cam_row_take(cur.pcr, pcv);
       if (!PF_PT) {
         const size_t b = 3 * (size_t)(tl.pt_begin + lp_raw);
 #pragma unroll
@@ -308,34 +307,23 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
 #pragma unroll
       for (int k = 0; k < 3; ++k) yp[k] = (S)0;
       if (act) {
-        if constexpr (RJ) {
-          // blocks applied in factored form from the camera and the point;
-          // a robust loss weights q (J^T W J p)
-          const Cam<S> cam = prod_cam<S>(cur.crow);
-          const S* pc = cur.crow + kProdCamP;
-          const S qwq = wts != nullptr
-                            ? snavely_apply<true, S>(cam, cur.xj[0], cur.xj[1], cur.xj[2], pc, cur.pjv, cur.wgt, yc, yp)
-                            : snavely_apply<false, S>(cam, cur.xj[0], cur.xj[1], cur.xj[2], pc, cur.pjv, (S)1, yc, yp);
-          pap += (double)qwq;
-        } else {
-          const S(&col)[12][2] = cur.col;
-          S q0 = (S)0, q1 = (S)0;
+        const S(&col)[12][2] = cur.col;
+        S q0 = (S)0, q1 = (S)0;
 #pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            q0 = fma(col[k][0], cur.pcv[k], q0);
-            q1 = fma(col[k][1], cur.pcv[k], q1);
-          }
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            q0 = fma(col[9 + k][0], cur.pjv[k], q0);
-            q1 = fma(col[9 + k][1], cur.pjv[k], q1);
-          }
-          pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
-#pragma unroll
-          for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
+        for (int k = 0; k < 9; ++k) {
+          q0 = fma(col[k][0], pcv[k], q0);
+          q1 = fma(col[k][1], pcv[k], q1);
         }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          q0 = fma(col[9 + k][0], cur.pjv[k], q0);
+          q1 = fma(col[9 + k][1], cur.pjv[k], q1);
+        }
+        pap = fma((double)q0, (double)q0, fma((double)q1, (double)q1, pap));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) yc[k] = fma(col[k][0], q0, col[k][1] * q1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) yp[k] = fma(col[9 + k][0], q0, col[9 + k][1] * q1);
         // LDS sums: the most observed cameras into their private copies,
         // the other hot cameras, and the cold cameras of this workgroup's
         // window
@@ -399,7 +387,7 @@ __global__ __launch_bounds__((MvCfg<S, RJ>::threads)) void k_matvec(
       tln = tlnn;
       mn = mnn;
       tlnn = tl3;
-      if (!RJ && !PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), nxt.col);
+      if (!PREFETCH_J) JStore<S>::load(J, tl.obs_begin + olane(n), nxt.col);
       return false;
     };
     for (;;) {
@@ -793,7 +781,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   constexpr int T_FULL = MvCfg<S, RJ>::threads;
   const int P = std::min(h->K, kPrivCams);
   const size_t lds = matvec_lds_bytes(h->K, h->L);
-  auto kern = k_matvec<S, RJ>;
+  auto kern = k_matvec<S>;
   // recomputed blocks run the point-per-lane kernel, in small workgroups on
   // a small problem
   const bool small = RJ && h->mv_small;
@@ -833,8 +821,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
                         (const S*)h->vec.D, lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows,
                         (S*)h->cold_rows, h->win_rows, h->split_rows, h->partials, scp, P, h->L,
                         h->cold_local_base, (unsigned)(3 * (size_t)h->np * sizeof(S)),
-                        (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)),
-                        RJ ? weights_of<S>(h) : static_cast<const S*>(nullptr));
+                        (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)));
   CBA_LAUNCHED();
 }
 

@@ -78,8 +78,118 @@ __device__ inline Cam<T> load_cam(const double* __restrict__ camtab, int c) {
   return cam;
 }
 
+// Quad-cooperative gather of 64-byte float32 rows (16 floats, the table
+// 64-byte aligned).  Gathering a row per lane takes four 16-byte requests,
+// each lane of each request at its own row; here request i fetches, for every
+// quad of lanes, the row of the quad's lane i, lane j of the quad taking
+// quarter j, so that a request touches one row per quad instead of one per
+// lane.  quad_rows_take() then transposes the 4 x 4 quarters within the quad
+// (two rounds of lane swaps), leaving each lane its own row.  Both must run
+// with all lanes of the wave active, and the workgroup size must be a
+// multiple of 64.
+struct QuadRows {
+  float4 q[4];
+};
+
+__device__ inline void quad_rows_request(const float* __restrict__ tab, int row, QuadRows& r) {
+  const float4* t4 = reinterpret_cast<const float4*>(tab) + (threadIdx.x & 3u);
+  // quad_perm broadcasts of quad lanes 0..3
+  const int r0 = __builtin_amdgcn_mov_dpp(row, 0x00, 0xf, 0xf, false);
+  const int r1 = __builtin_amdgcn_mov_dpp(row, 0x55, 0xf, 0xf, false);
+  const int r2 = __builtin_amdgcn_mov_dpp(row, 0xaa, 0xf, 0xf, false);
+  const int r3 = __builtin_amdgcn_mov_dpp(row, 0xff, 0xf, 0xf, false);
+  r.q[0] = t4[4 * (size_t)r0];
+  r.q[1] = t4[4 * (size_t)r1];
+  r.q[2] = t4[4 * (size_t)r2];
+  r.q[3] = t4[4 * (size_t)r3];
+}
+
+// One dword plane of the in-quad 4 x 4 transpose: lane j holds a_i = M[j][i]
+// and ends with a_i = M[i][j].  Round one swaps with lane j ^ 1 (pairs
+// (a0, a1), (a2, a3)), round two with lane j ^ 2 (pairs (a0, a2), (a1, a3)).
+__device__ inline float quad_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));
+}
+__device__ inline float quad_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4e, 0xf, 0xf, false));
+}
+__device__ inline void quad_swap(float& lo, float& hi, bool upper, bool two) {
+  const float s = upper ? lo : hi;
+  const float r = two ? quad_xor2(s) : quad_xor1(s);
+  lo = upper ? r : lo;
+  hi = upper ? hi : r;
+}
+__device__ inline void quad_transpose(float& a0, float& a1, float& a2, float& a3, bool b0, bool b1) {
+  quad_swap(a0, a1, b0, false);
+  quad_swap(a2, a3, b0, false);
+  quad_swap(a0, a2, b1, true);
+  quad_swap(a1, a3, b1, true);
+}
+
+__device__ inline void quad_rows_take(QuadRows& r, float (&v)[16]) {
+  const bool b0 = (threadIdx.x & 1u) != 0u, b1 = (threadIdx.x & 2u) != 0u;
+  quad_transpose(r.q[0].x, r.q[1].x, r.q[2].x, r.q[3].x, b0, b1);
+  quad_transpose(r.q[0].y, r.q[1].y, r.q[2].y, r.q[3].y, b0, b1);
+  quad_transpose(r.q[0].z, r.q[1].z, r.q[2].z, r.q[3].z, b0, b1);
+  quad_transpose(r.q[0].w, r.q[1].w, r.q[2].w, r.q[3].w, b0, b1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[4 * i] = r.q[i].x;
+    v[4 * i + 1] = r.q[i].y;
+    v[4 * i + 2] = r.q[i].z;
+    v[4 * i + 3] = r.q[i].w;
+  }
+}
+
+// A camera row of the working-precision table (16 values: R t f k1 k2 pad)
+// in two halves: cam_request() issues the loads (float32: quad-cooperative,
+// all lanes active), cam_take() turns what arrived into a camera (float32:
+// the in-quad transpose, all lanes active).
+template <typename T>
+struct CamReq;
+template <>
+struct CamReq<float> {
+  QuadRows r;
+};
+template <>
+struct CamReq<double> {
+  Cam<double> c;
+};
+template <typename T>
+__device__ inline void cam_request(const T* __restrict__ tab, int c, CamReq<T>& q);
+template <>
+__device__ inline void cam_request<double>(const double* __restrict__ tab, int c, CamReq<double>& q) {
+  q.c = load_cam<double>(tab, c);
+}
+template <>
+__device__ inline void cam_request<float>(const float* __restrict__ tab, int c, CamReq<float>& q) {
+  static_assert(kCamStride == 16, "64-byte float32 camera rows");
+  quad_rows_request(tab, c, q.r);
+}
+template <typename T>
+__device__ inline Cam<T> cam_take(CamReq<T>& q);
+template <>
+__device__ inline Cam<double> cam_take<double>(CamReq<double>& q) {
+  return q.c;
+}
+template <>
+__device__ inline Cam<float> cam_take<float>(CamReq<float>& q) {
+  float v[16];
+  quad_rows_take(q.r, v);
+  Cam<float> cam;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cam.R[i] = v[i];
+  cam.t[0] = v[9];
+  cam.t[1] = v[10];
+  cam.t[2] = v[11];
+  cam.f = v[12];
+  cam.k1 = v[13];
+  cam.k2 = v[14];
+  return cam;
+}
+
 // Camera row of the working-precision table (16 values: R t f k1 k2 pad),
-// read with 16-byte vector loads.
+// read with 16-byte vector loads, one row per lane.
 template <typename T>
 __device__ inline Cam<T> load_cam_s(const T* __restrict__ tab, int c);
 template <>
