@@ -255,6 +255,9 @@ struct caspar_ba {
   int* unit_pt = nullptr;        // [n_units] point | piece << 31 | first piece << 30
   int* unit_row = nullptr;       // [n_units] split row of a piece (-1 for whole points)
   int2* lane_tiles = nullptr;    // [n_lane_tiles] (trip count, first cold row)
+  int* lane_base = nullptr;      // [n_lane_tiles + 1] first step of each lane tile (sums of trip counts)
+  uint32_t* lane_meta = nullptr; // recomputed blocks: the meta word lane l of lane tile t reads at its step i,
+                                 // at (lane_base[t] + i) * 64 + l (coalesced per step)
   cba::SplitPoint* lane_split_pts = nullptr;
   double* lane_split_rows = nullptr;  // [pieces][kPtRowWidth] (3 used)
   void* hot_rows = nullptr;     // [G][K][9] per-workgroup hot-camera sums, working precision
@@ -318,7 +321,7 @@ struct Plan {
   Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, px_s, cm_px_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows, unit_obs, unit_pt,
-      unit_row, lane_tiles, lane_split_pts, lane_split_rows;
+      unit_row, lane_tiles, lane_split_pts, lane_split_rows, lane_base, lane_meta;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;

@@ -153,6 +153,10 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   take(p.lane_tiles, p.max_lane_tiles * 8 + 8);
   take(p.lane_split_pts, p.max_lane_split_pts * sizeof(SplitPoint) + 16);
   take(p.lane_split_rows, p.max_pieces * kPtRowWidth * 8 + 8);
+  // the point-per-lane kernels' meta words in their step order (recomputed
+  // blocks; a lane tile has at most kLaneObsMax steps)
+  take(p.lane_base, (p.max_lane_tiles + 1) * 4 + 4);
+  take(p.lane_meta, rj ? p.max_lane_tiles * kWave * kLaneObsMax * 4 + 16 : 16);
   p.total = off;
   return true;
 }
@@ -442,6 +446,32 @@ static std::vector<V> d2h(caspar_ba* h, const V* src, size_t n) {
     sync(h);
   }
   return out;
+}
+
+// Meta words of the point-per-lane kernels in their step order.  Lane l of
+// lane tile t holds unit 64 t + l (k observations) and at step i visits its
+// observation (i + l mod k) mod k; past its k observations, and on lanes past
+// the last unit (whose k is 0; they read the last unit's), its first one.
+// The word goes to (lane_base[t] + i) * 64 + l, so that the 64 lanes of a
+// step read 64 consecutive words.
+__global__ void k_lane_meta(int n_tiles, int n_units, const int* __restrict__ unit_obs,
+                            const int* __restrict__ lane_base, const uint32_t* __restrict__ meta,
+                            uint32_t* __restrict__ out) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_tiles * kWave) return;
+  const int t = (int)(gid / kWave), lane = (int)(gid % kWave);
+  const int u = t * kWave + lane;
+  const bool valid = u < n_units;
+  const int uc = valid ? u : n_units - 1;
+  const int ob = unit_obs[uc];
+  const int k = valid ? unit_obs[uc + 1] - ob : 0;
+  const int rot = k > 0 ? lane % k : 0;
+  const int b = lane_base[t], trip = lane_base[t + 1] - b;
+  for (int i = 0; i < trip; ++i) {
+    int j = i + rot;
+    if (j >= k) j -= k;
+    out[((size_t)b + i) * kWave + lane] = meta[i < k ? ob + j : ob];
+  }
 }
 
 static void build_layout(caspar_ba* h, const double* cams, const double* pts, const int* oc,
@@ -813,6 +843,19 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
   if (no) h2d(h, h->tiles, tiles);
   h2d(h, h->lane_tiles, lane_tiles);
 
+  // Recomputed blocks: the meta words of the point-per-lane kernels in their
+  // step order.
+  if (no && h->rj) {
+    std::vector<int> lbase(h->n_lane_tiles + 1, 0);
+    for (int t = 0; t < h->n_lane_tiles; ++t) lbase[t + 1] = lbase[t] + lane_tiles[t].x;
+    if ((size_t)lbase.back() > plan.max_lane_tiles * kLaneObsMax) fail(CASPAR_ENOMEM, "internal: lane steps exceed plan");
+    h2d(h, h->lane_base, lbase);
+    k_lane_meta<<<blocks_for((int64_t)h->n_lane_tiles * kWave, 256), 256, 0, st>>>(h->n_lane_tiles, h->n_units,
+                                                                                    h->unit_obs, h->lane_base,
+                                                                                    h->meta, h->lane_meta);
+    CBA_LAUNCHED();
+  }
+
   // Parameters.
   upload_cameras_bal(h, cams, h->cam);
   upload_points(h, pts, h->X);
@@ -959,6 +1002,8 @@ static int create_impl(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_
     h->lane_tiles = (int2*)(ws + plan.lane_tiles.off);
     h->lane_split_pts = (SplitPoint*)(ws + plan.lane_split_pts.off);
     h->lane_split_rows = (double*)(ws + plan.lane_split_rows.off);
+    h->lane_base = (int*)(ws + plan.lane_base.off);
+    h->lane_meta = (uint32_t*)(ws + plan.lane_meta.off);
     h->hot_rows = ws + plan.hot_rows.off;
     h->Hcc = (double*)(ws + plan.Hcc.off);
     h->Hpp = (double*)(ws + plan.Hpp.off);

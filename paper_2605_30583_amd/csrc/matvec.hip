@@ -433,12 +433,15 @@ __global__ __launch_bounds__((MvCfg<S, false>::threads)) void k_matvec(
 // (hot cameras, the window) or to cold rows exactly as in k_matvec, the rows
 // numbered per tile in (iteration, lane) order.  A whole point writes its row
 // of w directly (64 consecutive points per tile: coalesced); a piece writes a
-// split row that k_matvec_final adds up.
+// split row that k_matvec_final adds up.  The meta words come from a copy in
+// this step order (built at create), so the 64 reads of a step are one
+// coalesced request instead of 64 gathers.
 template <typename S, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     int n_tiles, int G, const int2* __restrict__ ltiles, int n_units, const int* __restrict__ unit_obs,
-    const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const uint32_t* __restrict__ meta,
-    const S* __restrict__ pts_s, const S* __restrict__ p_cam, const int* __restrict__ cold_lo,
+    const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const int* __restrict__ lbase,
+    const uint32_t* __restrict__ lmeta, const S* __restrict__ pts_s, const S* __restrict__ p_cam,
+    const int* __restrict__ cold_lo,
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows, double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L,
@@ -517,6 +520,10 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       return P;
     };
     auto tile_info = [&](int tt) { return ltiles[min(tt, n_tiles - 1)]; };
+    // first step of a tile in the step-ordered meta words (tiles past the
+    // last read the last one's first steps; their lanes have k = 0)
+    auto base_of = [&](int tt) { return lbase[min(tt, n_tiles - 1)]; };
+    auto meta_at = [&](int b, int i) { return lmeta[((size_t)b + i) * kWave + lane]; };
 
     Unit Uc = unit_at(t), Un = unit_at(t + WAVES), Unn = unit_at(t + 2 * WAVES);
     int2 ti_c = tile_info(t), ti_n = tile_info(t + WAVES);
@@ -525,9 +532,10 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     int cold_row = ti_c.y;
     S acc[3] = {(S)0, (S)0, (S)0};
     // step s (current), s + 1 and their observations; meta of s + 1
+    int b_c = base_of(t), b_n = base_of(t + WAVES);
     int o_c = obs_of(Uc, 0);
     int o_1 = obs_of(Uc, 1);  // trip >= 2
-    uint32_t m_1 = meta[o_1];
+    uint32_t m_1 = meta_at(b_c, 1);
     struct Row {
       S c[kProdCamRow];
       S wgt;
@@ -535,7 +543,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     };
     Row RA, RB;
     {
-      const uint32_t m0 = meta[o_c];
+      const uint32_t m0 = meta_at(b_c, 0);
       load_prod_cam<S>(p_cam, (int)(m0 & cmask), RA.c);
       RA.wgt = wts != nullptr ? wts[o_c] : (S)1;
       RA.cid = (int)(m0 & cmask);
@@ -552,7 +560,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       load_prod_cam<S>(p_cam, (int)(m_1 & cmask), nxt.c);
       nxt.wgt = wts != nullptr ? wts[o_1] : (S)1;
       nxt.cid = (int)(m_1 & cmask);
-      const uint32_t m_2 = meta[o_2];
+      const uint32_t m_2 = meta_at(in_tile2 ? b_c : b_n, in_tile2 ? it + 2 : it + 2 - ti_c.x);
       __builtin_amdgcn_sched_barrier(0);
       // step s
       const bool act = it < Uc.k;
@@ -620,6 +628,8 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       Pn = point_of(Un);
       ti_c = ti_n;
       ti_n = tile_info(t + WAVES);
+      b_c = b_n;
+      b_n = base_of(t + WAVES);
       cold_row = ti_c.y;
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[q] = (S)0;
@@ -808,7 +818,8 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   if constexpr (RJ) {
     hipExtLaunchKernelGGL(lanes, dim3(h->G), dim3(T), (uint32_t)lds, h->stream, e0, e1, 0u,
                           h->n_lane_tiles, h->G, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt, h->unit_row,
-                          h->meta, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p, (const S*)h->vec.D,
+                          h->lane_base, h->lane_meta, (const S*)pts_table(h), (const S*)h->p_cam, h->cold_lo, p,
+                          (const S*)h->vec.D,
                           lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows, (S*)h->cold_rows,
                           h->win_rows, h->lane_split_rows, h->partials, scp, P, h->L,
                           (unsigned)(3 * (size_t)h->np * sizeof(S)),
