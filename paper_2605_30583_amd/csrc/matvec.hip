@@ -435,8 +435,10 @@ __global__ __launch_bounds__((MvCfg<S, false>::threads)) void k_matvec(
 // of w directly (64 consecutive points per tile: coalesced); a piece writes a
 // split row that k_matvec_final adds up.  The meta words come from a copy in
 // this step order (built at create), so the 64 reads of a step are one
-// coalesced request instead of 64 gathers.
-template <typename S, int THREADS>
+// coalesced request instead of 64 gathers.  W: a robust loss's IRLS weights
+// (per observation, gathered by observation index); without them the kernel
+// tracks no observation indices at all.
+template <typename S, int THREADS, bool W>
 __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     int n_tiles, int G, const int2* __restrict__ ltiles, int n_units, const int* __restrict__ unit_obs,
     const int* __restrict__ unit_pt, const int* __restrict__ unit_row, const int* __restrict__ lbase,
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     {
       const uint32_t m0 = meta_at(b_c, 0);
       load_prod_cam<S>(p_cam, (int)(m0 & cmask), RA.c);
-      RA.wgt = wts != nullptr ? wts[o_c] : (S)1;
+      if constexpr (W) RA.wgt = wts[o_c];
       RA.cid = (int)(m0 & cmask);
     }
 
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       __builtin_amdgcn_sched_barrier(0);
       // requests: the row of step s + 1, the meta word of step s + 2
       load_prod_cam<S>(p_cam, (int)(m_1 & cmask), nxt.c);
-      nxt.wgt = wts != nullptr ? wts[o_1] : (S)1;
+      if constexpr (W) nxt.wgt = wts[o_1];
       nxt.cid = (int)(m_1 & cmask);
       const uint32_t m_2 = meta_at(in_tile2 ? b_c : b_n, in_tile2 ? it + 2 : it + 2 - ti_c.x);
       __builtin_amdgcn_sched_barrier(0);
@@ -572,9 +574,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       if (act) {
         const Cam<S> cam = prod_cam<S>(cur.c);
         const S* pc = cur.c + kProdCamP;
-        const S qwq = wts != nullptr
-                          ? snavely_apply<true, S>(cam, Pc.x[0], Pc.x[1], Pc.x[2], pc, Pc.p, cur.wgt, yc, yp)
-                          : snavely_apply<false, S>(cam, Pc.x[0], Pc.x[1], Pc.x[2], pc, Pc.p, (S)1, yc, yp);
+        const S qwq = snavely_apply<W, S>(cam, Pc.x[0], Pc.x[1], Pc.x[2], pc, Pc.p, W ? cur.wgt : (S)1, yc, yp);
         pap += (double)qwq;
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[q] += yp[q];
@@ -793,18 +793,21 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   const size_t lds = matvec_lds_bytes(h->K, h->L);
   auto kern = k_matvec<S>;
   // recomputed blocks run the point-per-lane kernel, in small workgroups on
-  // a small problem
+  // a small problem, with IRLS weights under a robust loss
   const bool small = RJ && h->mv_small;
-  auto lanes = small ? k_matvec_lanes<S, kLanesSmallThreads> : k_matvec_lanes<S, MvCfg<S, true>::threads>;
+  const bool wtd = RJ && weights_of<S>(h) != nullptr;
+  constexpr int TL = MvCfg<S, true>::threads;
+  auto lanes = small ? (wtd ? k_matvec_lanes<S, kLanesSmallThreads, true> : k_matvec_lanes<S, kLanesSmallThreads, false>)
+                     : (wtd ? k_matvec_lanes<S, TL, true> : k_matvec_lanes<S, TL, false>);
   const int T = small ? kLanesSmallThreads : T_FULL;
   const void* kptr = RJ ? (const void*)lanes : (const void*)kern;
   // the dynamic-LDS limit belongs to the kernel on a device: raised only when
   // a launch needs more than it was last set to (not at every launch)
   {
     static std::mutex mu;
-    static std::vector<size_t> lds_set[2];  // [full, small workgroups]
+    static std::vector<size_t> lds_set[4];  // [full, small workgroups] x [unweighted, weighted]
     std::lock_guard<std::mutex> lock(mu);
-    std::vector<size_t>& set = lds_set[small ? 1 : 0];
+    std::vector<size_t>& set = lds_set[(small ? 1 : 0) + (wtd ? 2 : 0)];
     if ((size_t)h->device >= set.size()) set.resize((size_t)h->device + 1, 65536);
     if (lds > set[h->device]) {
       CBA_HIP(hipFuncSetAttribute(kptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
