@@ -291,9 +291,10 @@ __device__ inline void pcg_scalars_after_update(DevScalars* sc, double a, double
 // LAST (a small problem, few workgroups): instead of a separate launch of
 // k_pcg_scalar1, the last workgroup to finish sums the partials and sets the
 // scalars.  Each workgroup takes a ticket with a device-scope release (its
-// partials, written by the same thread, become visible first); the one that
-// takes the last ticket acquires every workgroup's partials with a
-// device-scope acquire fence.  The release writes back the L2 of the
+// partials, written by the same thread, become visible first); the thread
+// that takes the last ticket acquires every workgroup's partials with a
+// device-scope acquire fence after its ticket read, and the workgroup barrier
+// passes them on to its other threads.  The release writes back the L2 of the
 // workgroup's XCD, which on a large problem (megabytes of r and z in flight)
 // costs more than the launch it saves.
 template <typename S, bool LAST>
@@ -363,12 +364,14 @@ __global__ __launch_bounds__(256) void k_pcg_update(int nc, int np, const S* __r
       // ticket: a write-back of the XCD's L2, no invalidate
       last = __hip_atomic_fetch_add(&sc->ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
              gridDim.x - 1;
+      // the last ticket's holder acquires every workgroup's partials: its
+      // ticket read is the atomic this fence pairs with (only the last
+      // workgroup invalidates its caches); the barrier below passes them on
+      // to the workgroup's other threads
+      if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (last) {
-      // acquire every workgroup's partials (only the last workgroup
-      // invalidates its L2)
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       double a = 0.0, c = 0.0;
       for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
         a += partials[(size_t)i * kPartialWidth];
