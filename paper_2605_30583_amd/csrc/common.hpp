@@ -51,8 +51,9 @@ constexpr int kCamRowWidth = 54;     // g_c (9) + upper triangle of H_cc (45)
 constexpr int kPtRowWidth = 9;       // g_p (3) + upper triangle of H_pp (6)
 constexpr int kColdRow = 10;         // doubles per cold-camera window row (9 sums, padded to 80 bytes)
 constexpr int kLdsBudget = 147456;   // bytes of LDS for hot-camera accumulators (144 KiB)
-constexpr int kPrivCams = 16;        // most observed cameras with private LDS copies in the product
-constexpr int kPrivCopies = 4;
+constexpr int kPrivCams = 12;        // most observed cameras with private LDS copies in the product
+constexpr int kPrivCopies = 8;       // (copy = lane mod 8; with 2048 hot cameras and the window, the LDS
+                                     // of a workgroup is then full to 128 bytes)
 constexpr int kColdWin = 128;        // cold cameras per product workgroup accumulated in its LDS window
 constexpr int kMaxHot = kLdsBudget / (9 * 8);  // 2048 cameras with float64 sums
 constexpr int kMaxPartials = 4096;   // per-workgroup partial slots
@@ -387,6 +388,11 @@ inline size_t matvec_lds_bytes(int K, int L) {
   const int P = K < kPrivCams ? K : kPrivCams;
   return ((size_t)K + (size_t)kPrivCopies * P + (size_t)L) * 9 * sizeof(double);
 }
+// the largest case, with the kernels' own reduction slots (16 doubles), fits
+// the 160 KiB of LDS a workgroup can have on gfx950
+static_assert(((size_t)kMaxHot + (size_t)kPrivCopies * kPrivCams + kColdWin) * 9 * sizeof(double) + 16 * 8 <=
+                  160 * 1024,
+              "product LDS exceeds 160 KiB");
 
 // Launch helpers implemented per translation unit (S = double or float).
 // layout.hip
