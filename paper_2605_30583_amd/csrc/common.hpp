@@ -259,6 +259,7 @@ struct caspar_ba {
   int* lane_base = nullptr;      // [n_lane_tiles + 1] first step of each lane tile (sums of trip counts)
   uint32_t* lane_meta = nullptr; // recomputed blocks: the meta word lane l of lane tile t reads at its step i,
                                  // at (lane_base[t] + i) * 64 + l (coalesced per step)
+  void* lane_wts = nullptr;      // recomputed blocks, robust loss: the IRLS weights in the same step order
   cba::SplitPoint* lane_split_pts = nullptr;
   double* lane_split_rows = nullptr;  // [pieces][kPtRowWidth] (3 used)
   void* hot_rows = nullptr;     // [G][K][9] per-workgroup hot-camera sums, working precision
@@ -322,7 +323,7 @@ struct Plan {
   Region cam, cam_trial, cam_s, cam_trial_s, pts_s, wts, px_s, cm_px_s, X, X_trial, cam_c2i, cam_i2c, pt_c2i, pt_i2c, obs_s2c, meta, px, J,
       tiles, cold_lo, p_cam, cm_obs, cm_pt, cm_px, cam_off, chunks, chunk_off, chunk_rows, cold_list, cold_off, cold_rows,
       split_pts, split_rows, hot_rows, Hcc, Hpp, Mc, Mp, vecs, partials, scal, gauge_rows, unit_obs, unit_pt,
-      unit_row, lane_tiles, lane_split_pts, lane_split_rows, lane_base, lane_meta;
+      unit_row, lane_tiles, lane_split_pts, lane_split_rows, lane_base, lane_meta, lane_wts;
   size_t vec_bytes = 0;
   int K = 0, G = 0;
   size_t max_tiles = 0, max_chunks = 0, max_cold = 0, max_split_tiles = 0, max_split_pts = 0;
@@ -343,6 +344,11 @@ inline size_t scalar_bytes(int prec) { return prec == CASPAR_FP64 ? 8 : 4; }
 template <typename S>
 inline const S* weights_of(const caspar_ba* h) {
   return h->loss == CASPAR_LOSS_TRIVIAL ? nullptr : static_cast<const S*>(h->wts);
+}
+// The same in the point-per-lane product's step order (recomputed blocks).
+template <typename S>
+inline const S* lane_weights_of(const caspar_ba* h) {
+  return h->loss == CASPAR_LOSS_TRIVIAL ? nullptr : static_cast<const S*>(h->lane_wts);
 }
 
 // Layout of the product's camera rows of p: stride of a row and offset of
@@ -400,6 +406,7 @@ void upload_cameras_bal(caspar_ba* h, const double* cams_bal_caller, double* cam
 void upload_points(caspar_ba* h, const double* pts_caller, double* X_internal);
 // linearize.hip
 void run_linearize(caspar_ba* h);                   // J, g, H, D, cost, gmax
+void launch_lane_weights(caspar_ba* h);             // IRLS weights into the product's step order
 double run_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  // F at params
 void launch_cost(caspar_ba* h, const double* cam, const double* X, bool fp64);  // its sums, no read-back
 double cost_of(const caspar_ba* h, const DevScalars& s);  // F from the sums launch_cost left

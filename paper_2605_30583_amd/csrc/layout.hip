@@ -157,6 +157,7 @@ bool make_plan(int nc, int np, int64_t no, int mode, Plan& p) {
   // blocks; a lane tile has at most kLaneObsMax steps)
   take(p.lane_base, (p.max_lane_tiles + 1) * 4 + 4);
   take(p.lane_meta, rj ? p.max_lane_tiles * kWave * kLaneObsMax * 4 + 16 : 16);
+  take(p.lane_wts, rj ? p.max_lane_tiles * kWave * kLaneObsMax * s + 16 : 16);
   p.total = off;
   return true;
 }
@@ -448,15 +449,17 @@ static std::vector<V> d2h(caspar_ba* h, const V* src, size_t n) {
   return out;
 }
 
-// Meta words of the point-per-lane kernels in their step order.  Lane l of
-// lane tile t holds unit 64 t + l (k observations) and at step i visits its
-// observation (i + l mod k) mod k; past its k observations, and on lanes past
-// the last unit (whose k is 0; they read the last unit's), its first one.
-// The word goes to (lane_base[t] + i) * 64 + l, so that the 64 lanes of a
-// step read 64 consecutive words.
-__global__ void k_lane_meta(int n_tiles, int n_units, const int* __restrict__ unit_obs,
-                            const int* __restrict__ lane_base, const uint32_t* __restrict__ meta,
-                            uint32_t* __restrict__ out) {
+// Per-observation values (the meta words at create, the IRLS weights after
+// each robust linearisation) in the point-per-lane product's step order.
+// Lane l of lane tile t holds unit 64 t + l (k observations) and at step i
+// visits its observation (i + l mod k) mod k; past its k observations, and on
+// lanes past the last unit (whose k is 0; they read the last unit's), its
+// first one.  The value goes to (lane_base[t] + i) * 64 + l, so that the 64
+// lanes of a step read 64 consecutive values.
+template <typename T>
+__global__ void k_lane_order(int n_tiles, int n_units, const int* __restrict__ unit_obs,
+                             const int* __restrict__ lane_base, const T* __restrict__ meta,
+                             T* __restrict__ out) {
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= (int64_t)n_tiles * kWave) return;
   const int t = (int)(gid / kWave), lane = (int)(gid % kWave);
@@ -472,6 +475,18 @@ __global__ void k_lane_meta(int n_tiles, int n_units, const int* __restrict__ un
     if (j >= k) j -= k;
     out[((size_t)b + i) * kWave + lane] = meta[i < k ? ob + j : ob];
   }
+}
+
+void launch_lane_weights(caspar_ba* h) {
+  if (!h->rj || h->n_lane_tiles == 0) return;
+  const unsigned g = blocks_for((int64_t)h->n_lane_tiles * kWave, 256);
+  if (h->prec == CASPAR_FP64)
+    k_lane_order<double><<<g, 256, 0, h->stream>>>(h->n_lane_tiles, h->n_units, h->unit_obs, h->lane_base,
+                                                   (const double*)h->wts, (double*)h->lane_wts);
+  else
+    k_lane_order<float><<<g, 256, 0, h->stream>>>(h->n_lane_tiles, h->n_units, h->unit_obs, h->lane_base,
+                                                  (const float*)h->wts, (float*)h->lane_wts);
+  CBA_LAUNCHED();
 }
 
 static void build_layout(caspar_ba* h, const double* cams, const double* pts, const int* oc,
@@ -850,9 +865,8 @@ static void build_layout(caspar_ba* h, const double* cams, const double* pts, co
     for (int t = 0; t < h->n_lane_tiles; ++t) lbase[t + 1] = lbase[t] + lane_tiles[t].x;
     if ((size_t)lbase.back() > plan.max_lane_tiles * kLaneObsMax) fail(CASPAR_ENOMEM, "internal: lane steps exceed plan");
     h2d(h, h->lane_base, lbase);
-    k_lane_meta<<<blocks_for((int64_t)h->n_lane_tiles * kWave, 256), 256, 0, st>>>(h->n_lane_tiles, h->n_units,
-                                                                                    h->unit_obs, h->lane_base,
-                                                                                    h->meta, h->lane_meta);
+    k_lane_order<uint32_t><<<blocks_for((int64_t)h->n_lane_tiles * kWave, 256), 256, 0, st>>>(
+        h->n_lane_tiles, h->n_units, h->unit_obs, h->lane_base, h->meta, h->lane_meta);
     CBA_LAUNCHED();
   }
 
@@ -1004,6 +1018,7 @@ static int create_impl(caspar_ba** out, int32_t n_cams, int32_t n_points, int64_
     h->lane_split_rows = (double*)(ws + plan.lane_split_rows.off);
     h->lane_base = (int*)(ws + plan.lane_base.off);
     h->lane_meta = (uint32_t*)(ws + plan.lane_meta.off);
+    h->lane_wts = ws + plan.lane_wts.off;
     h->hot_rows = ws + plan.hot_rows.off;
     h->Hcc = (double*)(ws + plan.Hcc.off);
     h->Hpp = (double*)(ws + plan.Hpp.off);

@@ -721,10 +721,14 @@ static void linearize_t(caspar_ba* h) {
   const S* ptab = (const S*)pts_table(h);
   if (h->rj ? h->n_lane_tiles > 0 : h->n_tiles > 0) {
     if (h->rj)
+    {
       k_lin_lanes<S><<<tg, 256, 0, st>>>(h->n_lane_tiles, h->lane_tiles, h->n_units, h->unit_obs, h->unit_pt,
                                          h->unit_row, h->meta, pixels_of<S>(h), camtab, ptab, g, D, h->Hpp,
                                          h->lane_split_rows, h->nc, h->partials, h->loss, h->loss_c, (S*)h->wts);
-    else
+      CBA_LAUNCHED();
+      // the product reads the IRLS weights in its step order
+      if (h->loss != CASPAR_LOSS_TRIVIAL) launch_lane_weights(h);
+    } else
       k_lin_points<S, true><<<tg, 256, 0, st>>>(h->n_tiles, h->tiles, h->meta, pixels_of<S>(h), camtab, ptab, h->J, g, D,
                                                 h->Hpp, h->split_rows, h->nc, h->partials, h->loss, h->loss_c,
                                                 (S*)h->wts);

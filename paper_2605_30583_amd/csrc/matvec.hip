@@ -426,7 +426,8 @@ __global__ __launch_bounds__((MvCfg<S, false>::threads)) void k_matvec(
 // piece of one with more.  Lane l takes unit 64 t + l, loads its point's X,
 // p and D once, and loops over the unit's observations (trip count: the
 // tile's largest unit), keeping the point sum J_p^T q in registers; the
-// observation of iteration i is (i + l) mod k: neighbouring lanes take
+// observation of iteration i is (i + l) mod k (an order fixed at create, see
+// the step-ordered tables below): neighbouring lanes take
 // different ranks of their points' camera lists (each sorted by camera),
 // so the lanes of one LDS access that hit the same camera (the most observed
 // one, or the tile's shared least observed one) are spread over the wave.  Camera sums go to LDS
@@ -435,9 +436,8 @@ __global__ __launch_bounds__((MvCfg<S, false>::threads)) void k_matvec(
 // of w directly (64 consecutive points per tile: coalesced); a piece writes a
 // split row that k_matvec_final adds up.  The meta words come from a copy in
 // this step order (built at create), so the 64 reads of a step are one
-// coalesced request instead of 64 gathers.  W: a robust loss's IRLS weights
-// (per observation, gathered by observation index); without them the kernel
-// tracks no observation indices at all.
+// coalesced request instead of 64 gathers.  W: a robust loss's IRLS weights,
+// which come in the same step order (copied there after each linearisation).
 template <typename S, int THREADS, bool W>
 __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     int n_tiles, int G, const int2* __restrict__ ltiles, int n_units, const int* __restrict__ unit_obs,
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     const S* __restrict__ p, const S* __restrict__ D, double lambda, S* __restrict__ w, int nc, int K,
     int n_orphan, S* __restrict__ hot_rows, S* __restrict__ cold_rows, double* __restrict__ win_rows,
     double* __restrict__ split_rows, double* __restrict__ partials, DevScalars* __restrict__ sc, int P, int L,
-    unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ wts) {
+    unsigned w_pt_bytes, unsigned cold_bytes, const S* __restrict__ lwts) {
   constexpr int WAVES = THREADS / kWave;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* hot = reinterpret_cast<double*>(lds_raw);        // [K][9] camera sums
@@ -485,8 +485,11 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
   // next two, and the point data (X, p, D) for this tile and the next.
   int t = t0 + __builtin_amdgcn_readfirstlane(wv);
   if (t < t1) {
+    // (the observation a lane visits at a step is fixed at create: the meta
+    // words and IRLS weights come in step order, so the kernel needs only the
+    // unit's observation count)
     struct Unit {
-      int ob, k, rot;
+      int k;
       unsigned ptw;
     };
     // lanes of a tile past the range (or past the last unit) get k = 0 and
@@ -496,16 +499,9 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       const int u = tt * kWave + lane;
       const bool valid = tt < t1 && u < n_units;
       const int uc = valid ? u : n_units - 1;
-      U.ob = unit_obs[uc];
-      U.k = valid ? unit_obs[uc + 1] - U.ob : 0;
+      U.k = valid ? unit_obs[uc + 1] - unit_obs[uc] : 0;
       U.ptw = valid ? (unsigned)unit_pt[uc] : 0u;
-      U.rot = U.k > 0 ? lane % U.k : 0;
       return U;
-    };
-    auto obs_of = [&](const Unit& U, int i) {
-      int j = i + U.rot;
-      if (j >= U.k) j -= U.k;
-      return i < U.k ? U.ob + j : U.ob;
     };
     struct Pt {
       S x[3], p[3], d[3];
@@ -526,6 +522,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     // last read the last one's first steps; their lanes have k = 0)
     auto base_of = [&](int tt) { return lbase[min(tt, n_tiles - 1)]; };
     auto meta_at = [&](int b, int i) { return lmeta[((size_t)b + i) * kWave + lane]; };
+    auto wgt_at = [&](int b, int i) { return lwts[((size_t)b + i) * kWave + lane]; };
 
     Unit Uc = unit_at(t), Un = unit_at(t + WAVES), Unn = unit_at(t + 2 * WAVES);
     int2 ti_c = tile_info(t), ti_n = tile_info(t + WAVES);
@@ -535,9 +532,7 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     S acc[3] = {(S)0, (S)0, (S)0};
     // step s (current), s + 1 and their observations; meta of s + 1
     int b_c = base_of(t), b_n = base_of(t + WAVES);
-    int o_c = obs_of(Uc, 0);
-    int o_1 = obs_of(Uc, 1);  // trip >= 2
-    uint32_t m_1 = meta_at(b_c, 1);
+    uint32_t m_1 = meta_at(b_c, 1);  // trip >= 2
     struct Row {
       S c[kProdCamRow];
       S wgt;
@@ -547,20 +542,19 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
     {
       const uint32_t m0 = meta_at(b_c, 0);
       load_prod_cam<S>(p_cam, (int)(m0 & cmask), RA.c);
-      if constexpr (W) RA.wgt = wts[o_c];
+      if constexpr (W) RA.wgt = wgt_at(b_c, 0);
       RA.cid = (int)(m0 & cmask);
     }
 
     // One step: compute step s from cur while step s + 1's row comes into
     // nxt.  Returns true after the wave's last step.
     auto step = [&](Row& cur, Row& nxt) -> bool {
-      // the step after next: this tile or the next
-      const bool in_tile2 = it + 2 < ti_c.x;
-      const int o_2 = in_tile2 ? obs_of(Uc, it + 2) : obs_of(Un, it + 2 - ti_c.x);
+      // the next step and the one after: this tile or the next
+      const bool in_tile1 = it + 1 < ti_c.x, in_tile2 = it + 2 < ti_c.x;
       __builtin_amdgcn_sched_barrier(0);
       // requests: the row of step s + 1, the meta word of step s + 2
       load_prod_cam<S>(p_cam, (int)(m_1 & cmask), nxt.c);
-      if constexpr (W) nxt.wgt = wts[o_1];
+      if constexpr (W) nxt.wgt = wgt_at(in_tile1 ? b_c : b_n, in_tile1 ? it + 1 : 0);
       nxt.cid = (int)(m_1 & cmask);
       const uint32_t m_2 = meta_at(in_tile2 ? b_c : b_n, in_tile2 ? it + 2 : it + 2 - ti_c.x);
       __builtin_amdgcn_sched_barrier(0);
@@ -595,7 +589,6 @@ __global__ __launch_bounds__(THREADS) void k_matvec_lanes(
       }
       cold_row += (int)__popcll(sm);
       // advance
-      o_1 = o_2;
       m_1 = m_2;
       if (++it < ti_c.x) return false;
       // end of the tile: the point's row of w (whole points) or its split row
@@ -795,7 +788,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
   // recomputed blocks run the point-per-lane kernel, in small workgroups on
   // a small problem, with IRLS weights under a robust loss
   const bool small = RJ && h->mv_small;
-  const bool wtd = RJ && weights_of<S>(h) != nullptr;
+  const bool wtd = RJ && lane_weights_of<S>(h) != nullptr;
   constexpr int TL = MvCfg<S, true>::threads;
   auto lanes = small ? (wtd ? k_matvec_lanes<S, kLanesSmallThreads, true> : k_matvec_lanes<S, kLanesSmallThreads, false>)
                      : (wtd ? k_matvec_lanes<S, TL, true> : k_matvec_lanes<S, TL, false>);
@@ -826,7 +819,7 @@ static void launch_matvec(caspar_ba* h, double lambda, const S* p, S* w, DevScal
                           lambda, w, h->nc, h->K, h->n_orphan_pts, (S*)h->hot_rows, (S*)h->cold_rows,
                           h->win_rows, h->lane_split_rows, h->partials, scp, P, h->L,
                           (unsigned)(3 * (size_t)h->np * sizeof(S)),
-                          (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)), weights_of<S>(h));
+                          (unsigned)((size_t)h->cold_local_base * ColdRow<S>::n * sizeof(S)), lane_weights_of<S>(h));
     CBA_LAUNCHED();
     return;
   }
