@@ -173,8 +173,8 @@ CASPAR_API int caspar_ba_create(caspar_ba** out, int32_t n_cams, int32_t n_point
  * pinned-host allocation (scalar read-backs go through the handle's own host
  * memory, so solves poll a little slower than with create()).  Problems
  * whose caspar_ba_workspace_bytes() exceeds 256 MiB get CASPAR_ENOMEM (about
- * 1.5 million observations in CASPAR_FP32_MIXED | CASPAR_RECOMPUTE_JACOBIAN
- * mode at 6.5 observations per point; about 1.3 million with stored blocks
+ * 1.4 million observations in CASPAR_FP32_MIXED | CASPAR_RECOMPUTE_JACOBIAN
+ * mode at 6.5 observations per point; about 1.2 million with stored blocks
  * or float64 and recomputed blocks, 0.8 million in float64 with stored
  * blocks).  The array belongs to one
  * handle at a time on each GPU: while a handle created this way lives, a
