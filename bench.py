@@ -36,8 +36,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-# Float32 / float64 vector FMA issue without packed math (this build does not
-# use packed float32): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+# Float32 / float64 vector FMA issue without packed math (the library is
+# compiled without packed float32): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic flops of the fused product per observation (FMA = 2).
 # Stored blocks: q = J p (48), J_c^T q and J_p^T q (36), |q|^2 and the
