@@ -1,6 +1,7 @@
 """caspar_ba_create_static: the handle built on the library's static device
 workspace (no device allocation) gives the results of caspar_ba_create on
-the same inputs, on two calls in a row (the second problem smaller), and
+the same inputs, on two calls in a row (the second problem smaller) and on a
+third with a robust loss (its IRLS weights live in the workspace too), and
 refuses a second static handle on the same GPU and problems beyond the
 array's size."""
 import ctypes as C
@@ -25,12 +26,15 @@ def _static_handle(sc, px, precision, rj):
                           precision, recompute_jacobian=rj, static_workspace=True)
 
 
-def _compare(sc, precision, rj, golden=None):
+def _compare(sc, precision, rj, golden=None, loss=None):
     from paper_2605_30583_amd import SolveOptions
     px = observed_pixels(sc)
     a = _static_handle(sc, px, precision, rj)
     b = handle_for(sc, px, precision, rj=rj)
     try:
+        if loss is not None:
+            a.set_loss(*loss)
+            b.set_loss(*loss)
         la, lb = a.linearize(), b.linearize()
         assert abs(la["cost"] - lb["cost"]) <= 1e-12 * lb["cost"]
         for k in ("resid", "jac_cam", "jac_pt", "grad", "diag"):
@@ -72,6 +76,10 @@ def test_static_workspace_matches_create_on_two_calls():
     # second call, smaller problem, other Jacobian mode, after the first released the array
     b = _compare(small, 0, True)
     b.close()
+    # third call: a robust loss, whose weights (per observation and in the
+    # product's step order) are in the array as well
+    c = _compare(small, 0, True, loss=("huber", 1.0))
+    c.close()
     # beyond the array's size: refused before any input is read
     h = C.c_void_p()
     st = lib.caspar_ba_create_static(C.byref(h), 1000, 10_000_000, 60_000_000, None, None, None, None, None, 0,
