@@ -55,6 +55,31 @@ def test_linearize_and_product_match_oracle(scene, kind, rj):
         assert abs(pap - p @ ref) <= 1e-12 * abs(p @ ref)
 
 
+@pytest.mark.parametrize("rj", [False, True], ids=["stored", "recompute"])
+@pytest.mark.parametrize("kind", ["huber", "cauchy"])
+def test_fp32_mixed_weighted_product_matches_oracle(scene, kind, rj):
+    """The weighted product in the float32-mixed form, whose IRLS weights the
+    recomputed-block product reads from its step-ordered copy: a wrong or
+    stale weight changes J^T W J p directly (a solve could still converge to
+    the same optimum by other steps).  Bar: float32 blocks and products, as
+    for the unweighted mixed product."""
+    sc, px = scene
+    ba = handle_for(sc, px, 1, rj=rj)
+    ba.set_loss(kind, SCALE)
+    ba.linearize(outputs=False)
+    st = camera.State.from_bal(sc.cams_init, sc.points_init)
+    _, r, Jc, Jp, w = robust.linearize(st, sc.obs_cam, sc.obs_pt, px, kind, SCALE)
+    J = linear.jacobian_csr(Jc, Jp, sc.obs_cam, sc.obs_pt, st.n_cams, st.n_points)
+    D = linear.damping_diagonal(J)
+    rng = np.random.default_rng(4)
+    for lam in (1e-4, 1e-1):
+        p = rng.normal(size=st.n_params)
+        wv, pap = ba.matvec(lam, t64(p))
+        ref = linear.matvec(J, D, lam, p)
+        assert rel(wv.cpu(), ref) <= 2e-5
+        assert abs(pap - p @ ref) <= 2e-5 * abs(p @ ref)
+
+
 def _solve(name, precision=0, rj=False):
     from paper_2605_30583_amd import SolveOptions
     g = GOLDEN[name]
