@@ -115,6 +115,44 @@ def test_large_workload_with_between_factors(large, precision, tol):
     ba.close()
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-5)])
+def test_large_workload_huber(large, precision, tol):
+    """The benchmark's robust run: a Huber loss at 3 px on the same workload,
+    recomputed blocks.  The robust cost over every observation against the
+    oracle's, and the IRLS-scaled gradient, damping diagonal and product at
+    the sampled columns.  The product reads each observation's weight from the
+    copy laid out in the order the lanes visit their observations, so a weight
+    taken for the wrong observation anywhere in the sampled rows shows here.
+    Bars as for the plain loss: the weights only scale the blocks."""
+    from oracle import robust
+    sc, px, st0, cost, cams, pts = large
+    scale = 3.0
+    ba = handle_for(sc, px, precision, rj=True)
+    ba.set_loss("huber", scale)
+    lin = ba.linearize()
+    F = 0.0
+    step = 4_000_000
+    for b in range(0, sc.n_obs, step):      # bounded host memory
+        F += robust.cost(st0, sc.obs_cam[b:b + step], sc.obs_pt[b:b + step], px[b:b + step], "huber", scale)
+    assert F < cost                          # some observations are down-weighted
+    assert abs(lin["cost"] - F) <= tol * F
+    lam = 1e-2
+    p = np.random.default_rng(5).normal(size=9 * sc.n_cams + 3 * sc.n_points)
+    w, _ = ba.matvec(lam, t64(p))
+    rows = np.isin(sc.obs_cam, cams) | np.isin(sc.obs_pt, pts)
+    oc, op = sc.obs_cam[rows], sc.obs_pt[rows]
+    _, r, Jc, Jp, wts = robust.linearize(st0, oc, op, px[rows], "huber", scale)
+    assert wts.min() < 1.0
+    J = linear.jacobian_csr(Jc, Jp, oc, op, sc.n_cams, sc.n_points)
+    D = linear.damping_diagonal(J)
+    cols = np.concatenate([(9 * cams[:, None] + np.arange(9)).ravel(),
+                           (9 * sc.n_cams + 3 * pts[:, None] + np.arange(3)).ravel()])
+    assert rel(lin["grad"].cpu().numpy()[cols], linear.gradient(J, r.ravel())[cols]) <= tol
+    assert rel(lin["diag"].cpu().numpy()[cols], D[cols]) <= tol
+    assert rel(w.cpu().numpy()[cols], linear.matvec(J, D, lam, p)[cols]) <= tol
+    ba.close()
+
+
 def test_large_workload_pcg_residual(large):
     """The solve's inner step at full size, as the benchmark runs it
     (float32-mixed, recomputed blocks, tolerance 1e-3): the float64 residual
