@@ -455,7 +455,9 @@ static std::vector<V> d2h(caspar_ba* h, const V* src, size_t n) {
 // visits its observation (i + l mod k) mod k; past its k observations, and on
 // lanes past the last unit (whose k is 0; they read the last unit's), its
 // first one.  The value goes to (lane_base[t] + i) * 64 + l, so that the 64
-// lanes of a step read 64 consecutive values.
+// lanes of a step read 64 consecutive values.  The cold-row numbering built at
+// create walks each tile's cameras in this same order, so the two change
+// together.
 template <typename T>
 __global__ void k_lane_order(int n_tiles, int n_units, const int* __restrict__ unit_obs,
                              const int* __restrict__ lane_base, const T* __restrict__ meta,
