@@ -115,10 +115,11 @@ def test_large_workload_with_between_factors(large, precision, tol):
     ba.close()
 
 
+@pytest.mark.parametrize("kind", ["huber", "cauchy"])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-5)])
-def test_large_workload_huber(large, precision, tol):
-    """The benchmark's robust run: a Huber loss at 3 px on the same workload,
-    recomputed blocks.  The robust cost over every observation against the
+def test_large_workload_robust(large, precision, tol, kind):
+    """The benchmark's robust run (a Huber loss at 3 px) and a Cauchy loss at
+    the same scale on the same workload, recomputed blocks.  The robust cost over every observation against the
     oracle's, and the IRLS-scaled gradient, damping diagonal and product at
     the sampled columns.  The product reads each observation's weight from the
     copy laid out in the order the lanes visit their observations, so a weight
@@ -128,12 +129,12 @@ def test_large_workload_huber(large, precision, tol):
     sc, px, st0, cost, cams, pts = large
     scale = 3.0
     ba = handle_for(sc, px, precision, rj=True)
-    ba.set_loss("huber", scale)
+    ba.set_loss(kind, scale)
     lin = ba.linearize()
     F = 0.0
     step = 4_000_000
     for b in range(0, sc.n_obs, step):      # bounded host memory
-        F += robust.cost(st0, sc.obs_cam[b:b + step], sc.obs_pt[b:b + step], px[b:b + step], "huber", scale)
+        F += robust.cost(st0, sc.obs_cam[b:b + step], sc.obs_pt[b:b + step], px[b:b + step], kind, scale)
     assert F < cost                          # some observations are down-weighted
     assert abs(lin["cost"] - F) <= tol * F
     lam = 1e-2
@@ -141,7 +142,7 @@ def test_large_workload_huber(large, precision, tol):
     w, _ = ba.matvec(lam, t64(p))
     rows = np.isin(sc.obs_cam, cams) | np.isin(sc.obs_pt, pts)
     oc, op = sc.obs_cam[rows], sc.obs_pt[rows]
-    _, r, Jc, Jp, wts = robust.linearize(st0, oc, op, px[rows], "huber", scale)
+    _, r, Jc, Jp, wts = robust.linearize(st0, oc, op, px[rows], kind, scale)
     assert wts.min() < 1.0
     J = linear.jacobian_csr(Jc, Jp, oc, op, sc.n_cams, sc.n_points)
     D = linear.damping_diagonal(J)
@@ -151,7 +152,7 @@ def test_large_workload_huber(large, precision, tol):
             "grad": rel(lin["grad"].cpu().numpy()[cols], linear.gradient(J, r.ravel())[cols]),
             "diag": rel(lin["diag"].cpu().numpy()[cols], D[cols]),
             "product": rel(w.cpu().numpy()[cols], linear.matvec(J, D, lam, p)[cols])}
-    print("huber, precision", precision, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    print(kind, "precision", precision, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert max(errs.values()) <= tol
     ba.close()
 
